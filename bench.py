@@ -1,0 +1,211 @@
+"""Benchmark of the stoichiometry-matrix chemistry hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the paper-sized synthetic network (470 species, 4600 reactions,
+shaped like UMIST rate12 of Sec. 3) on 65,536 cells with T log-uniform on
+10-300 K and n_H log-uniform on 1e2-1e7 cm^-3, FP64, inputs resident in
+HBM before timing. A step evaluates dn/dt = S R(n, T) and the Jacobian for
+every cell (fused rate coefficients). Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector and matrix, published
+YEAR_S = 3.15576e7
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--cells", type=int, default=65536)
+    p.add_argument("--layout", default="sell")
+    p.add_argument("--ordering", default="nnz")
+    p.add_argument("--no-table", action="store_true", help="skip the layout x ordering table")
+    p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    return p.parse_args()
+
+
+class Timer:
+    """HIP events around launches on torch's current stream (the stream the
+    library launches on), averaged per kernel name."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.ev = {}
+
+    def run(self, name, fn):
+        t = self.torch
+        a, b = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        self.ev.setdefault(name, []).append((a, b))
+
+    def mean_ms(self, name):
+        return float(np.mean([a.elapsed_time(b) for a, b in self.ev[name]]))
+
+
+def cpu_baseline(net, cells, seconds):
+    """The oracle (plain C, FP64, OpenMP over cells) on a bounded sample."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    oracle.set_threads(threads)
+    # size the sample from a short probe so the run takes about `seconds`
+    probe = min(64, cells.T.size)
+    t0 = time.perf_counter()
+    oracle.rhs(net, cells.y0[:probe], cells.T[:probe])
+    oracle.jac_dense(net, cells.y0[:probe], cells.T[:probe])
+    dt = max(time.perf_counter() - t0, 1e-6)
+    n = int(min(cells.T.size, max(probe, probe * seconds / dt)))
+    t0 = time.perf_counter()
+    for s in range(0, n, 256):
+        e = min(n, s + 256)
+        oracle.rhs(net, cells.y0[s:e], cells.T[s:e])
+        oracle.jac_dense(net, cells.y0[s:e], cells.T[s:e])
+    dt = time.perf_counter() - t0
+    return {"value": n * net.n_reactions / dt, "unit": "cell-reactions/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"RHS + dense Jacobian of the first {n} of the {cells.T.size} cells "
+                      f"({dt:.1f} s, {threads} threads)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(cells shard across GPUs with no communication; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    import synthnet
+    import paper_2312_04998_amd as acm
+
+    net, cells = synthnet.workload("medium", n_cells=args.cells)
+    ns, nr = net.n_species, net.n_reactions
+    dev = torch.device("cuda:0")
+    y = torch.from_numpy(cells.y0).to(dev)
+    T = torch.from_numpy(cells.T).to(dev)
+    N = acm.Network.from_synth(net, layout=args.layout, ordering=args.ordering)
+    dydt = torch.empty_like(y)
+    jv = torch.empty((args.cells, N.nnz_j), dtype=torch.float64, device=dev)
+    k = torch.empty((args.cells, nr), dtype=torch.float64, device=dev)
+    v = torch.randn(y.shape, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(0))
+    gy = torch.empty_like(y)
+    gl = torch.empty(nr, dtype=torch.float64, device=dev)
+
+    tm = Timer(torch)
+
+    def step():
+        tm.run("rhs", lambda: acm.ac_rhs(N, None, y, T, dydt))
+        tm.run("jac", lambda: acm.ac_jac(N, None, y, T, jv))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    tm.ev.clear()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+
+    # the other chemistry kernels of the path, timed the same way
+    for _ in range(2):
+        acm.ac_rates(N, None, T, k)
+        acm.ac_rhs_k(N, k, y, dydt)
+        acm.ac_vjp(N, None, y, T, v, gy, gl)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        tm.run("rates", lambda: acm.ac_rates(N, None, T, k))
+        tm.run("rhs_k", lambda: acm.ac_rhs_k(N, k, y, dydt))
+        tm.run("vjp", lambda: acm.ac_vjp(N, None, y, T, v, gy, gl))
+    torch.cuda.synchronize()
+
+    C = args.cells
+    kern = {}
+    # algorithmic bytes per launch: every input read once, every output written once
+    bytes_of = {
+        "rhs": C * (8 * ns * 2 + 8),
+        "jac": C * (8 * ns + 8 + 8 * N.nnz_j),
+        "rates": C * (8 + 8 * nr),
+        "rhs_k": C * (8 * nr + 16 * ns),
+        "vjp": C * (8 * ns * 3 + 8) + 8 * nr,
+    }
+    for name in ("rhs", "jac", "rates", "rhs_k", "vjp"):
+        ms = tm.mean_ms(name)
+        kern[name] = {"ms": round(ms, 4), "cell_reactions_per_s": C * nr / (ms * 1e-3),
+                      "GBps": bytes_of[name] / (ms * 1e-3) / 1e9,
+                      "hbm_frac": bytes_of[name] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+    table = {}
+    if not args.no_table:
+        for lay in ("csr", "sell", "coo"):
+            for order in ("natural", "nnz", "rcm"):
+                M = acm.Network.from_synth(net, layout=lay, ordering=order)
+                for _ in range(2):
+                    acm.ac_rhs(M, None, y, T, dydt)
+                torch.cuda.synchronize()
+                tt = Timer(torch)
+                for _ in range(5):
+                    tt.run("r", lambda: acm.ac_rhs(M, None, y, T, dydt))
+                torch.cuda.synchronize()
+                table[f"{lay}/{order}"] = round(C * nr / (tt.mean_ms("r") * 1e-3), 1)
+                M.close()
+
+    jac_ms = kern["jac"]["ms"]
+    achieved = bytes_of["jac"] / (jac_ms * 1e-3) / 1e9
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "jac_hbm_traffic.json")
+    if os.path.exists(tpath):
+        tr = json.load(open(tpath))
+        if tr.get("nnz_j") == N.nnz_j and tr.get("cells") == C:
+            traffic = tr.get("bytes_per_launch")
+    out = {
+        "metric": "RHS evals (cells×reactions)/s + integrated cells/s at rtol 1e-6 vs plain",
+        "value": C * nr / (ms_step * 1e-3),
+        "unit": "cell-reactions/s (RHS + Jacobian per step)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "470 species / 4600 reactions, 65,536 cells, RHS + Jacobian",
+                   "n_species": ns, "n_reactions": nr, "cells": C, "nnz_s": N.nnz_s,
+                   "nnz_j": N.nnz_j, "layout": args.layout, "ordering": args.ordering},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_jac",
+                     "bytes_per_launch": bytes_of["jac"], "avg_ms": jac_ms},
+        "kernels": kern,
+        "rhs_layout_table": table,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(net, cells, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/* astrochem: stoichiometry-matrix chemistry on MI355X (gfx950).
+ *
+ * C ABI of libastrochem.so. For many independent cells that share one
+ * reaction network it evaluates the chemical time derivative
+ *
+ *     dn/dt = S R(n, T),   R_j = k_j(T) * prod_{a in reactants(j)} n_a,
+ *     k_j(T) = alpha_j (T/300)^beta_j exp(-gamma_j / T),
+ *
+ * where S is the integer stoichiometry matrix (species x reactions; entry
+ * (i, j) is how much species i changes in reaction j -- the matrix form of
+ * Motoyama et al., Sec. 2.1, eq. matrix-form), its Jacobian S dR/dn,
+ * vector-Jacobian products, a batched stiff BDF integrator and its discrete
+ * adjoint.
+ *
+ * Conventions shared by every entry point:
+ *  - Per-cell arrays are DEVICE pointers owned by the caller, laid out cell
+ *    by cell ([n_cells][n_species], each cell contiguous, species in the
+ *    natural order of the network description). Orderings chosen at network
+ *    creation only change the traversal inside the kernels.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL is the null stream)
+ *    and the call returns without synchronising. Argument errors are found
+ *    on the host before anything is enqueued.
+ *  - Every call returns an ac_status. No exception or abort crosses the ABI.
+ *    ac_last_error() gives a message for the last failure on the calling
+ *    thread.
+ *  - Network handles are immutable after creation and may be shared by
+ *    threads; calls that use a network's internal reduction buffer
+ *    (ac_vjp with g_logalpha) must not overlap on one network.
+ *  - All arithmetic is IEEE FP64 with denormals kept.
+ */
+#ifndef ASTROCHEM_H
+#define ASTROCHEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *ac_stream; /* a hipStream_t */
+
+typedef enum {
+  AC_OK = 0,
+  AC_EINVAL = 1,        /* bad argument (null pointer, size, index out of range, option) */
+  AC_ENOMEM = 2,        /* host or device allocation failed */
+  AC_EHIP = 3,          /* a HIP runtime call failed */
+  AC_EUNBALANCED = 4,   /* a reaction does not conserve elements/charge (check requested) */
+  AC_ECAPACITY = 5,     /* more cells than the workspace was created for */
+  AC_ELIMIT = 6         /* network exceeds a compiled limit (see AC_MAX_*) */
+} ac_status;
+
+/* Per-cell outcome of the integrator. */
+typedef enum {
+  AC_CELL_OK = 0,
+  AC_CELL_MAXSTEPS = 1,   /* step budget exhausted before t_end */
+  AC_CELL_HMIN = 2,       /* step size fell below 10 ulp(t) */
+  AC_CELL_BADINPUT = 3    /* T <= 0 or not finite, or an initial density < 0 or not finite */
+} ac_cell_status;
+
+/* Storage of S used by the RHS kernel (Sec. 2.2 compares COO, CCS, CRS and
+ * SELL on CPUs). Rows are split into chunks of at most `chunk` nonzeros so
+ * that heavy species rows are shared by many lanes. */
+typedef enum {
+  AC_LAYOUT_CSR = 0,   /* row chunks with contiguous nonzeros (CRS) */
+  AC_LAYOUT_SELL = 1,  /* sliced ELLPACK over row chunks: slices of sell_c chunks,
+                          nonzero k of every chunk of a slice stored together, chunks
+                          sorted by length within windows of sell_sigma (SELL-C-sigma) */
+  AC_LAYOUT_COO = 2    /* coordinate triplets, scattered with LDS atomics
+                          (summation order not reproducible run to run) */
+} ac_layout;
+
+/* Order in which species rows are traversed (Sec. 3 reorders rows by their
+ * number of nonzeros). */
+typedef enum {
+  AC_ORDER_NATURAL = 0,
+  AC_ORDER_NNZ_DESC = 1,  /* most nonzeros first, ties in natural order */
+  AC_ORDER_RCM = 2        /* reverse Cuthill-McKee on the species graph of S S^T */
+} ac_ordering;
+
+#define AC_MAX_SPECIES 2047
+#define AC_MAX_REACTIONS 65536
+#define AC_MAX_REACTANTS 2
+#define AC_MAX_PRODUCTS 4
+
+typedef struct {
+  int32_t n_species;
+  int32_t n_reactions;
+  const int32_t *reactants;  /* host [n_reactions][2]: species index or -1; A + A listed twice;
+                                at least one reactant per reaction */
+  const int32_t *products;   /* host [n_reactions][4]: species index or -1 */
+  const double *alpha;       /* host [n_reactions], > 0 */
+  const double *beta;        /* host [n_reactions] */
+  const double *gamma;       /* host [n_reactions] */
+  const int8_t *composition; /* host [n_species][n_elem] element/charge counts, or NULL */
+  int32_t n_elem;
+  int32_t check_balance;     /* nonzero: fail with AC_EUNBALANCED unless E S = 0 exactly */
+  int32_t layout;            /* ac_layout */
+  int32_t ordering;          /* ac_ordering */
+  int32_t chunk;             /* max nonzeros per row chunk; 0 = default (32) */
+  int32_t sell_c;            /* SELL slice width in chunks; 0 = default (64, one wavefront) */
+  int32_t sell_sigma;        /* SELL sorting window in chunks; 0 = default (whole matrix) */
+} ac_net_desc;
+
+typedef struct ac_net ac_net;
+
+/* Builds a network (Sec. 2.1: S from the reactant/product lists, net
+ * entries only, so a catalyst A in A + B -> A + C has S = 0 but still enters
+ * R and the Jacobian) together with its row storage, traversal order, the
+ * symbolic pattern of the Jacobian and the per-entry contribution lists, and
+ * uploads them to the current device. All arrays are copied. Without a
+ * visible device the handle is host-only: the queries below work and every
+ * kernel entry point returns AC_EHIP. */
+ac_status ac_net_create(const ac_net_desc *desc, ac_net **out);
+ac_status ac_net_destroy(ac_net *net);
+
+/* Sizes: nonzeros of S, nonzeros of the Jacobian pattern, Jacobian
+ * contribution terms, row chunks of the RHS storage. Any pointer may be NULL. */
+ac_status ac_net_info(const ac_net *net, int64_t *nnz_s, int64_t *nnz_j, int64_t *n_contrib,
+                      int64_t *n_chunks);
+
+/* Host copies of S in CSR (natural species rows, reactions ascending) and of
+ * the Jacobian pattern (CSR, natural rows, columns ascending). Output arrays
+ * are caller-owned host memory of the sizes ac_net_info reports. */
+ac_status ac_net_stoich(const ac_net *net, int32_t *row_ptr /*n_species+1*/,
+                        int32_t *reaction /*nnz_s*/, int32_t *value /*nnz_s*/);
+ac_status ac_net_jac_pattern(const ac_net *net, int32_t *row_ptr /*n_species+1*/,
+                             int32_t *col /*nnz_j*/);
+/* Traversal order of species rows (perm[k] = species visited k-th). */
+ac_status ac_net_row_order(const ac_net *net, int32_t *perm /*n_species*/);
+
+/* Host-side storage builder for any small integer matrix given densely
+ * (row-major n_rows x n_cols), exposing the formats of Sec. 2.2 with
+ * 0-based indices:
+ *   AC_FMT_COO: val, idx = column, idx2 = row, in row-major order
+ *   AC_FMT_CCS: val, idx = row, ptr = column pointers (n_cols+1)
+ *   AC_FMT_CRS: val, idx = column, ptr = row pointers (n_rows+1)
+ *   AC_FMT_SELL: slices of `width` rows (no splitting, no sorting); inside a
+ *     slice nonzero k of every row is stored before nonzero k+1; short rows
+ *     are padded with value 0 and a valid column; ptr = slice lengths
+ *     (n_slices), idx = column.
+ * *n_val is the capacity of val/idx/idx2 on entry and the count on return
+ * (AC_EINVAL if too small). */
+enum { AC_FMT_COO = 0, AC_FMT_CCS = 1, AC_FMT_CRS = 2, AC_FMT_SELL = 3 };
+ac_status ac_sparse_format(int32_t n_rows, int32_t n_cols, const int32_t *dense, int32_t fmt,
+                           int32_t width, int64_t *n_val, int32_t *val, int32_t *idx,
+                           int32_t *idx2, int32_t *ptr);
+
+/* ---------------------------------------------------------------- kernels
+ * log_alpha: optional DEVICE [n_reactions] override of ln(alpha) (for
+ * differentiation); NULL uses the network's own coefficients. */
+
+/* k[c][j] = alpha_j (T_c/300)^beta_j exp(-gamma_j/T_c), the coefficients the
+ * paper precomputes outside the stiff solver (Sec. 3). k: [n_cells][n_reactions]. */
+ac_status ac_rates(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *T,
+                   double *k, ac_stream stream);
+
+/* dydt = S R(y, T) per cell (eq. matrix-form), coefficients computed on the
+ * fly. y, dydt: [n_cells][n_species]; T: [n_cells]. */
+ac_status ac_rhs(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *y,
+                 const double *T, double *dydt, ac_stream stream);
+
+/* Same with precomputed coefficients k [n_cells][n_reactions]. */
+ac_status ac_rhs_k(const ac_net *net, int64_t n_cells, const double *k, const double *y,
+                   double *dydt, ac_stream stream);
+
+/* Jacobian values on the fixed pattern (ac_net_jac_pattern):
+ * jvals[c][e] = d(dydt_i)/d(y_a) for pattern entry e = (i, a).
+ * jvals: [n_cells][nnz_j]. */
+ac_status ac_jac(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *y,
+                 const double *T, double *jvals, ac_stream stream);
+
+/* Vector-Jacobian products for cotangents v [n_cells][n_species]:
+ *   gy[c][a] = sum_i v[c][i] J_ia                            (gy may be NULL)
+ *   g_logalpha[j] = sum_c sum_i v[c][i] d(dydt_i)/d(ln alpha_j)
+ *                 = sum_c R_cj (S^T v_c)_j                     (may be NULL)
+ * The cell sum is formed in a fixed order (reproducible bit for bit). */
+ac_status ac_vjp(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *y,
+                 const double *T, const double *v, double *gy, double *g_logalpha,
+                 ac_stream stream);
+
+/* Status text and the calling thread's last error message (incl. HIP's). */
+const char *ac_status_string(ac_status s);
+int ac_last_error(char *buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,290 @@
+"""Python binding of libastrochem.so (stoichiometry-matrix chemistry on MI355X).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels. PyTorch supplies device memory (tensors) and the current stream.
+The functions keep the C names (ac_rhs, ac_jac, ...); `Network` wraps a
+network handle. Importing this package never falls back to another
+implementation: if the built library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libastrochem.so")
+
+AC_OK, AC_EINVAL, AC_ENOMEM, AC_EHIP, AC_EUNBALANCED, AC_ECAPACITY, AC_ELIMIT = range(7)
+AC_LAYOUT_CSR, AC_LAYOUT_SELL, AC_LAYOUT_COO = 0, 1, 2
+AC_ORDER_NATURAL, AC_ORDER_NNZ_DESC, AC_ORDER_RCM = 0, 1, 2
+AC_FMT_COO, AC_FMT_CCS, AC_FMT_CRS, AC_FMT_SELL = 0, 1, 2, 3
+AC_CELL_OK, AC_CELL_MAXSTEPS, AC_CELL_HMIN, AC_CELL_BADINPUT = 0, 1, 2, 3
+LAYOUTS = {"csr": AC_LAYOUT_CSR, "sell": AC_LAYOUT_SELL, "coo": AC_LAYOUT_COO}
+ORDERINGS = {"natural": AC_ORDER_NATURAL, "nnz": AC_ORDER_NNZ_DESC, "rcm": AC_ORDER_RCM}
+
+
+class AstrochemError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+class NetDesc(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32),
+                ("reactants", C.c_void_p), ("products", C.c_void_p),
+                ("alpha", C.c_void_p), ("beta", C.c_void_p), ("gamma", C.c_void_p),
+                ("composition", C.c_void_p), ("n_elem", C.c_int32),
+                ("check_balance", C.c_int32), ("layout", C.c_int32), ("ordering", C.c_int32),
+                ("chunk", C.c_int32), ("sell_c", C.c_int32), ("sell_sigma", C.c_int32)]
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2312_04998_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, st = C.c_void_p, C.c_int32, C.c_int64, C.c_int
+    sig = {
+        "ac_net_create": [vp, vp],
+        "ac_net_destroy": [vp],
+        "ac_net_info": [vp, vp, vp, vp, vp],
+        "ac_net_stoich": [vp, vp, vp, vp],
+        "ac_net_jac_pattern": [vp, vp, vp],
+        "ac_net_row_order": [vp, vp],
+        "ac_sparse_format": [i32, i32, vp, i32, i32, vp, vp, vp, vp, vp],
+        "ac_rates": [vp, vp, i64, vp, vp, vp],
+        "ac_rhs": [vp, vp, i64, vp, vp, vp, vp],
+        "ac_rhs_k": [vp, i64, vp, vp, vp, vp],
+        "ac_jac": [vp, vp, i64, vp, vp, vp, vp],
+        "ac_vjp": [vp, vp, i64, vp, vp, vp, vp, vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = st
+    L.ac_status_string.argtypes = [st]
+    L.ac_status_string.restype = C.c_char_p
+    L.ac_last_error.argtypes = [C.c_char_p, C.c_size_t]
+    L.ac_last_error.restype = C.c_int
+    for name in ("ac_ws_create", "ac_ws_destroy", "ac_integrate", "ac_integrate_adjoint",
+                 "ac_integrate_plain"):
+        if hasattr(L, name):
+            getattr(L, name).restype = st
+    return L
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    buf = C.create_string_buffer(4096)
+    lib.ac_last_error(buf, 4096)
+    return buf.value.decode(errors="replace")
+
+
+def check(status: int, where: str) -> None:
+    if status != AC_OK:
+        raise AstrochemError(status, where, last_error())
+
+
+def _ptr(t) -> Optional[int]:
+    """Device (or host numpy) address of a tensor/array, or None."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is not None:
+        return int(stream)
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _check_dev(t, shape, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Network:
+    """Owns an ac_net handle built from a reaction list (arrays as in
+    synthnet.Network: reactants [nr,2], products [nr,4], alpha/beta/gamma)."""
+
+    def __init__(self, reactants, products, alpha, beta, gamma, composition=None,
+                 layout: str = "csr", ordering: str = "natural", chunk: int = 0, sell_c: int = 0,
+                 sell_sigma: int = 0, check_balance: bool = False):
+        self._rea = np.ascontiguousarray(reactants, np.int32)
+        self._pro = np.ascontiguousarray(products, np.int32)
+        self._a = np.ascontiguousarray(alpha, np.float64)
+        self._b = np.ascontiguousarray(beta, np.float64)
+        self._g = np.ascontiguousarray(gamma, np.float64)
+        self._comp = None if composition is None else np.ascontiguousarray(composition, np.int8)
+        self.n_reactions = int(self._rea.shape[0])
+        if composition is not None:
+            self.n_species = int(self._comp.shape[0])
+        else:
+            self.n_species = int(max(self._rea.max(), self._pro.max())) + 1
+        self.layout, self.ordering = layout, ordering
+        d = NetDesc(self.n_species, self.n_reactions, _ptr(self._rea), _ptr(self._pro),
+                    _ptr(self._a), _ptr(self._b), _ptr(self._g), _ptr(self._comp),
+                    0 if self._comp is None else self._comp.shape[1], int(check_balance),
+                    LAYOUTS[layout], ORDERINGS[ordering], chunk, sell_c, sell_sigma)
+        h = C.c_void_p()
+        check(lib.ac_net_create(C.byref(d), C.byref(h)), "ac_net_create")
+        self.handle = h
+        nnz_s, nnz_j, nco, nch = (C.c_int64() for _ in range(4))
+        check(lib.ac_net_info(h, C.byref(nnz_s), C.byref(nnz_j), C.byref(nco), C.byref(nch)),
+              "ac_net_info")
+        self.nnz_s, self.nnz_j, self.n_contrib, self.n_chunks = (
+            nnz_s.value, nnz_j.value, nco.value, nch.value)
+
+    @classmethod
+    def from_synth(cls, net, **kw):
+        return cls(net.reactants, net.products, net.alpha, net.beta, net.gamma,
+                   composition=net.composition, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.ac_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------- host queries
+    def stoich_csr(self):
+        rp = np.zeros(self.n_species + 1, np.int32)
+        rx = np.zeros(max(self.nnz_s, 1), np.int32)
+        va = np.zeros(max(self.nnz_s, 1), np.int32)
+        check(lib.ac_net_stoich(self.handle, _ptr(rp), _ptr(rx), _ptr(va)), "ac_net_stoich")
+        return rp, rx[:self.nnz_s], va[:self.nnz_s]
+
+    def jac_pattern(self):
+        rp = np.zeros(self.n_species + 1, np.int32)
+        col = np.zeros(max(self.nnz_j, 1), np.int32)
+        check(lib.ac_net_jac_pattern(self.handle, _ptr(rp), _ptr(col)), "ac_net_jac_pattern")
+        return rp, col[:self.nnz_j]
+
+    def row_order(self):
+        p = np.zeros(self.n_species, np.int32)
+        check(lib.ac_net_row_order(self.handle, _ptr(p)), "ac_net_row_order")
+        return p
+
+    # --------------------------------------------------------- device calls
+    def rates(self, T, log_alpha=None, out=None, stream=None):
+        import torch
+        n = T.shape[0]
+        out = torch.empty((n, self.n_reactions), dtype=torch.float64, device=T.device) if out is None else out
+        ac_rates(self, log_alpha, T, out, stream)
+        return out
+
+    def rhs(self, y, T, log_alpha=None, out=None, stream=None):
+        import torch
+        out = torch.empty_like(y) if out is None else out
+        ac_rhs(self, log_alpha, y, T, out, stream)
+        return out
+
+    def rhs_k(self, k, y, out=None, stream=None):
+        import torch
+        out = torch.empty_like(y) if out is None else out
+        ac_rhs_k(self, k, y, out, stream)
+        return out
+
+    def jac(self, y, T, log_alpha=None, out=None, stream=None):
+        import torch
+        out = torch.empty((y.shape[0], self.nnz_j), dtype=torch.float64, device=y.device) if out is None else out
+        ac_jac(self, log_alpha, y, T, out, stream)
+        return out
+
+    def vjp(self, y, T, v, log_alpha=None, want_gy=True, want_glog=True, stream=None):
+        import torch
+        gy = torch.empty_like(y) if want_gy else None
+        gl = torch.empty(self.n_reactions, dtype=torch.float64, device=y.device) if want_glog else None
+        ac_vjp(self, log_alpha, y, T, v, gy, gl, stream)
+        return gy, gl
+
+
+# ------------------------------------------------------------ C-named calls
+
+def _cells(net: Network, y, T):
+    n = T.shape[0]
+    _check_dev(T, (n,), "T")
+    if y is not None:
+        _check_dev(y, (n, net.n_species), "y")
+    return n
+
+
+def ac_rates(net: Network, log_alpha, T, k, stream=None):
+    n = _cells(net, None, T)
+    _check_dev(k, (n, net.n_reactions), "k")
+    if log_alpha is not None:
+        _check_dev(log_alpha, (net.n_reactions,), "log_alpha")
+    check(lib.ac_rates(net.handle, _ptr(log_alpha), n, _ptr(T), _ptr(k), _stream(stream)), "ac_rates")
+
+
+def ac_rhs(net: Network, log_alpha, y, T, dydt, stream=None):
+    n = _cells(net, y, T)
+    _check_dev(dydt, (n, net.n_species), "dydt")
+    if log_alpha is not None:
+        _check_dev(log_alpha, (net.n_reactions,), "log_alpha")
+    check(lib.ac_rhs(net.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T), _ptr(dydt),
+                     _stream(stream)), "ac_rhs")
+
+
+def ac_rhs_k(net: Network, k, y, dydt, stream=None):
+    n = k.shape[0]
+    _check_dev(k, (n, net.n_reactions), "k")
+    _check_dev(y, (n, net.n_species), "y")
+    _check_dev(dydt, (n, net.n_species), "dydt")
+    check(lib.ac_rhs_k(net.handle, n, _ptr(k), _ptr(y), _ptr(dydt), _stream(stream)), "ac_rhs_k")
+
+
+def ac_jac(net: Network, log_alpha, y, T, jvals, stream=None):
+    n = _cells(net, y, T)
+    _check_dev(jvals, (n, net.nnz_j), "jvals")
+    if log_alpha is not None:
+        _check_dev(log_alpha, (net.n_reactions,), "log_alpha")
+    check(lib.ac_jac(net.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T), _ptr(jvals),
+                     _stream(stream)), "ac_jac")
+
+
+def ac_vjp(net: Network, log_alpha, y, T, v, gy, g_logalpha, stream=None):
+    n = _cells(net, y, T)
+    _check_dev(v, (n, net.n_species), "v")
+    if gy is not None:
+        _check_dev(gy, (n, net.n_species), "gy")
+    if g_logalpha is not None:
+        _check_dev(g_logalpha, (net.n_reactions,), "g_logalpha")
+    if log_alpha is not None:
+        _check_dev(log_alpha, (net.n_reactions,), "log_alpha")
+    check(lib.ac_vjp(net.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T), _ptr(v), _ptr(gy),
+                     _ptr(g_logalpha), _stream(stream)), "ac_vjp")
+
+
+def ac_sparse_format(dense, fmt: int, width: int = 0):
+    """Host storage builder (Sec. 2.2 formats) for a small integer matrix."""
+    A = np.ascontiguousarray(dense, np.int32)
+    nr, nc = A.shape
+    cap = C.c_int64(4 * nr * nc + 16)
+    val = np.zeros(cap.value, np.int32)
+    idx = np.zeros(cap.value, np.int32)
+    idx2 = np.zeros(cap.value, np.int32)
+    ptr = np.zeros(nr + nc + 2, np.int32)
+    check(lib.ac_sparse_format(nr, nc, _ptr(A), fmt, width, C.byref(cap), _ptr(val), _ptr(idx),
+                               _ptr(idx2), _ptr(ptr)), "ac_sparse_format")
+    n = cap.value
+    return val[:n], idx[:n], idx2[:n], ptr

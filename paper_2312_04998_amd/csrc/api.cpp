@@ -1,0 +1,370 @@
+// C ABI of libastrochem.so: argument checks, network upload, launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/astrochem.h"
+#include "devnet.h"
+#include "netbuild.h"
+
+struct ac_net {
+  ac::HostNet host;
+  ac::DNet d{};
+  void *dbuf = nullptr;
+  double *vjp_part = nullptr;   // [vjp_rows][n_reactions] per-workgroup partial sums
+  int vjp_rows = 0;
+  int device = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+ac_status fail(ac_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+ac_status hip_fail(hipError_t e, const char *what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return AC_EHIP;
+}
+
+// Packs host vectors into one device allocation (256-byte aligned pieces).
+struct Packer {
+  struct Piece { const void *src; size_t bytes; size_t off; };
+  std::vector<Piece> pieces;
+  size_t total = 0;
+  template <typename T>
+  size_t add(const std::vector<T> &v) {
+    size_t off = total;
+    pieces.push_back({v.data(), v.size() * sizeof(T), off});
+    total += (v.size() * sizeof(T) + 255) / 256 * 256;
+    if (v.empty()) total += 256;
+    return off;
+  }
+};
+
+template <typename T>
+const T *at(void *base, size_t off) {
+  return reinterpret_cast<const T *>(static_cast<char *>(base) + off);
+}
+
+struct SchedOff {
+  size_t seg_out, seg_chunk, chunk_ptr, chunk_dst, multi_out, multi_slot, items, slice_ptr,
+      sell_chunk, sell_len, sell_items, coo_out;
+};
+
+SchedOff add_sched(Packer &p, const ac::Schedule &s) {
+  SchedOff o;
+  o.seg_out = p.add(s.seg_out);
+  o.seg_chunk = p.add(s.seg_chunk);
+  o.chunk_ptr = p.add(s.chunk_ptr);
+  o.chunk_dst = p.add(s.chunk_dst);
+  o.multi_out = p.add(s.multi_out);
+  o.multi_slot = p.add(s.multi_slot);
+  o.items = p.add(s.items);
+  o.slice_ptr = p.add(s.slice_ptr);
+  o.sell_chunk = p.add(s.sell_chunk);
+  o.sell_len = p.add(s.sell_len);
+  o.sell_items = p.add(s.sell_items);
+  o.coo_out = p.add(s.coo_out);
+  return o;
+}
+
+ac::DSched dev_sched(void *b, const ac::Schedule &s, const SchedOff &o) {
+  ac::DSched d{};
+  d.n_seg = s.n_seg;
+  d.n_chunk = s.n_chunk;
+  d.n_item = s.n_item;
+  d.n_slot = s.n_slot;
+  d.n_multi = s.n_multi;
+  d.seg_out = at<int32_t>(b, o.seg_out);
+  d.seg_chunk = at<int32_t>(b, o.seg_chunk);
+  d.chunk_ptr = at<int32_t>(b, o.chunk_ptr);
+  d.chunk_dst = at<int32_t>(b, o.chunk_dst);
+  d.multi_out = at<int32_t>(b, o.multi_out);
+  d.multi_slot = at<int32_t>(b, o.multi_slot);
+  d.items = at<uint32_t>(b, o.items);
+  d.sell_c = s.sell_c;
+  d.n_slice = s.n_slice;
+  d.slice_ptr = at<int32_t>(b, o.slice_ptr);
+  d.sell_chunk = at<int32_t>(b, o.sell_chunk);
+  d.sell_len = at<int32_t>(b, o.sell_len);
+  d.sell_items = at<uint32_t>(b, o.sell_items);
+  d.coo_out = at<int32_t>(b, o.coo_out);
+  return d;
+}
+
+constexpr int VJP_ROWS = 512;   // fixed VJP grid: the cell-to-workgroup map never changes
+
+}  // namespace
+
+extern "C" {
+
+const char *ac_status_string(ac_status s) {
+  switch (s) {
+    case AC_OK: return "ok";
+    case AC_EINVAL: return "invalid argument";
+    case AC_ENOMEM: return "out of memory";
+    case AC_EHIP: return "HIP runtime error";
+    case AC_EUNBALANCED: return "reaction does not conserve elements/charge";
+    case AC_ECAPACITY: return "workspace capacity exceeded";
+    case AC_ELIMIT: return "network exceeds a compiled limit";
+  }
+  return "unknown status";
+}
+
+int ac_last_error(char *buf, size_t n) {
+  if (buf && n) {
+    size_t m = std::min(n - 1, g_err.size());
+    std::memcpy(buf, g_err.data(), m);
+    buf[m] = 0;
+  }
+  return int(g_err.size());
+}
+
+ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
+  if (!desc || !out) return fail(AC_EINVAL, "null argument");
+  *out = nullptr;
+  ac_net *net = new (std::nothrow) ac_net();
+  if (!net) return fail(AC_ENOMEM, "host allocation failed");
+  int code = 0;
+  std::string err;
+  try {
+    err = ac::build_network(desc->n_species, desc->n_reactions, desc->reactants, desc->products,
+                            desc->alpha, desc->beta, desc->gamma, desc->composition, desc->n_elem,
+                            desc->check_balance != 0, desc->layout, desc->ordering, desc->chunk,
+                            desc->sell_c, desc->sell_sigma, net->host, &code);
+  } catch (const std::bad_alloc &) {
+    delete net;
+    return fail(AC_ENOMEM, "host allocation failed during network build");
+  }
+  if (!err.empty()) {
+    delete net;
+    return fail(ac_status(code), err);
+  }
+  const ac::HostNet &H = net->host;
+  Packer p;
+  const size_t o_la = p.add(H.log_alpha), o_be = p.add(H.beta), o_ga = p.add(H.gamma);
+  const size_t o_rp = p.add(H.rpair);
+  const size_t o_cp = p.add(H.s_col_ptr), o_cr = p.add(H.s_row), o_cv = p.add(H.s_cval);
+  const SchedOff o_rhs = add_sched(p, H.rhs), o_jac = add_sched(p, H.jac), o_gy = add_sched(p, H.gy);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    *out = net;   // host-only handle: queries work, kernels report AC_EHIP
+    return AC_OK;
+  }
+  hipGetDevice(&net->device);
+  hipError_t e = hipMalloc(&net->dbuf, p.total);
+  if (e != hipSuccess) {
+    delete net;
+    return hip_fail(e, "hipMalloc(network)");
+  }
+  std::vector<char> staging(p.total, 0);
+  for (auto &pc : p.pieces)
+    if (pc.bytes) std::memcpy(staging.data() + pc.off, pc.src, pc.bytes);
+  e = hipMemcpy(net->dbuf, staging.data(), p.total, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    net->vjp_rows = VJP_ROWS;
+    e = hipMalloc(&net->vjp_part, sizeof(double) * size_t(VJP_ROWS) * H.nr);
+  }
+  if (e != hipSuccess) {
+    hipFree(net->dbuf);
+    delete net;
+    return hip_fail(e, "network upload");
+  }
+  void *b = net->dbuf;
+  ac::DNet &d = net->d;
+  d.ns = H.ns;
+  d.nr = H.nr;
+  d.nnz_j = int(H.j_col.size());
+  d.layout = H.layout;
+  d.log_alpha = at<double>(b, o_la);
+  d.beta = at<double>(b, o_be);
+  d.gamma = at<double>(b, o_ga);
+  d.rpair = at<uint32_t>(b, o_rp);
+  d.s_col_ptr = at<int32_t>(b, o_cp);
+  d.s_row = at<int32_t>(b, o_cr);
+  d.s_cval = at<int32_t>(b, o_cv);
+  d.rhs = dev_sched(b, H.rhs, o_rhs);
+  d.jac = dev_sched(b, H.jac, o_jac);
+  d.gy = dev_sched(b, H.gy, o_gy);
+  *out = net;
+  return AC_OK;
+}
+
+ac_status ac_net_destroy(ac_net *net) {
+  if (!net) return AC_OK;
+  hipFree(net->dbuf);
+  hipFree(net->vjp_part);
+  delete net;
+  return AC_OK;
+}
+
+ac_status ac_net_info(const ac_net *net, int64_t *nnz_s, int64_t *nnz_j, int64_t *n_contrib,
+                      int64_t *n_chunks) {
+  if (!net) return fail(AC_EINVAL, "null network");
+  if (nnz_s) *nnz_s = int64_t(net->host.s_col.size());
+  if (nnz_j) *nnz_j = int64_t(net->host.j_col.size());
+  if (n_contrib) *n_contrib = int64_t(net->host.jac.n_item);
+  if (n_chunks) *n_chunks = int64_t(net->host.rhs.n_chunk);
+  return AC_OK;
+}
+
+ac_status ac_net_stoich(const ac_net *net, int32_t *row_ptr, int32_t *reaction, int32_t *value) {
+  if (!net || !row_ptr || !reaction || !value) return fail(AC_EINVAL, "null argument");
+  const auto &H = net->host;
+  std::copy(H.s_row_ptr.begin(), H.s_row_ptr.end(), row_ptr);
+  std::copy(H.s_col.begin(), H.s_col.end(), reaction);
+  std::copy(H.s_val.begin(), H.s_val.end(), value);
+  return AC_OK;
+}
+
+ac_status ac_net_jac_pattern(const ac_net *net, int32_t *row_ptr, int32_t *col) {
+  if (!net || !row_ptr || !col) return fail(AC_EINVAL, "null argument");
+  std::copy(net->host.j_row_ptr.begin(), net->host.j_row_ptr.end(), row_ptr);
+  std::copy(net->host.j_col.begin(), net->host.j_col.end(), col);
+  return AC_OK;
+}
+
+ac_status ac_net_row_order(const ac_net *net, int32_t *perm) {
+  if (!net || !perm) return fail(AC_EINVAL, "null argument");
+  std::copy(net->host.perm.begin(), net->host.perm.end(), perm);
+  return AC_OK;
+}
+
+ac_status ac_sparse_format(int32_t n_rows, int32_t n_cols, const int32_t *dense, int32_t fmt,
+                           int32_t width, int64_t *n_val, int32_t *val, int32_t *idx,
+                           int32_t *idx2, int32_t *ptr) {
+  if (n_rows <= 0 || n_cols <= 0 || !dense || !n_val || !val || !idx || !ptr)
+    return fail(AC_EINVAL, "null or empty argument");
+  std::vector<int32_t> v, ix, ix2, pt;
+  auto A = [&](int i, int j) { return dense[size_t(i) * n_cols + j]; };
+  if (fmt == AC_FMT_COO || fmt == AC_FMT_CRS) {
+    if (fmt == AC_FMT_CRS) pt.push_back(0);
+    for (int i = 0; i < n_rows; ++i) {
+      for (int j = 0; j < n_cols; ++j)
+        if (A(i, j)) {
+          v.push_back(A(i, j));
+          ix.push_back(j);
+          ix2.push_back(i);
+        }
+      if (fmt == AC_FMT_CRS) pt.push_back(int32_t(v.size()));
+    }
+    if (fmt == AC_FMT_COO && !idx2) return fail(AC_EINVAL, "COO needs idx2");
+  } else if (fmt == AC_FMT_CCS) {
+    pt.push_back(0);
+    for (int j = 0; j < n_cols; ++j) {
+      for (int i = 0; i < n_rows; ++i)
+        if (A(i, j)) {
+          v.push_back(A(i, j));
+          ix.push_back(i);
+        }
+      pt.push_back(int32_t(v.size()));
+    }
+  } else if (fmt == AC_FMT_SELL) {
+    if (width <= 0) return fail(AC_EINVAL, "SELL needs a positive width");
+    // one chunk per row (no splitting), no sorting: the schedule builder
+    // with chunk = n_cols and sigma = 1
+    std::vector<std::vector<uint32_t>> seg(n_rows);
+    std::vector<std::vector<int>> vals(n_rows);
+    for (int i = 0; i < n_rows; ++i)
+      for (int j = 0; j < n_cols; ++j)
+        if (A(i, j)) {
+          seg[i].push_back(uint32_t(j));
+          vals[i].push_back(A(i, j));
+        }
+    std::vector<int32_t> order(n_rows);
+    for (int i = 0; i < n_rows; ++i) order[i] = i;
+    ac::Schedule s;
+    ac::build_schedule(seg, order, std::max(1, n_cols), width, 1, s);
+    for (int sl = 0; sl < s.n_slice; ++sl) {
+      const int w = (s.slice_ptr[sl + 1] - s.slice_ptr[sl]) / width;
+      pt.push_back(w);
+      for (int k = 0; k < w; ++k)
+        for (int l = 0; l < width; ++l) {
+          const int p = sl * width + l;
+          const int row = p < n_rows ? s.sell_chunk[p] : -1;
+          if (row >= 0 && k < int(vals[row].size())) {
+            v.push_back(vals[row][k]);
+            ix.push_back(int32_t(seg[row][k]));
+          } else {
+            // padding: value 0 with a valid column (the row's last one)
+            v.push_back(0);
+            ix.push_back(row >= 0 && !seg[row].empty() ? int32_t(seg[row].back()) : 0);
+          }
+        }
+    }
+  } else {
+    return fail(AC_EINVAL, "unknown format");
+  }
+  if (int64_t(v.size()) > *n_val) {
+    *n_val = int64_t(v.size());
+    return fail(AC_EINVAL, "output capacity too small");
+  }
+  *n_val = int64_t(v.size());
+  std::copy(v.begin(), v.end(), val);
+  std::copy(ix.begin(), ix.end(), idx);
+  if (fmt == AC_FMT_COO) std::copy(ix2.begin(), ix2.end(), idx2);
+  std::copy(pt.begin(), pt.end(), ptr);
+  return AC_OK;
+}
+
+// ----------------------------------------------------------------- kernels
+
+static ac_status check_cells(const ac_net *net, int64_t n_cells) {
+  if (!net) return fail(AC_EINVAL, "null network");
+  if (n_cells < 0) return fail(AC_EINVAL, "n_cells < 0");
+  if (!net->dbuf) return fail(AC_EHIP, "network has no device copy (no GPU at creation)");
+  return AC_OK;
+}
+
+ac_status ac_rates(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *T,
+                   double *k, ac_stream stream) {
+  if (ac_status s = check_cells(net, n_cells)) return s;
+  if (n_cells && (!T || !k)) return fail(AC_EINVAL, "null T or k");
+  hipError_t e = ac::launch_rates(net->d, log_alpha, n_cells, T, k, hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_rates launch");
+}
+
+ac_status ac_rhs(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *y,
+                 const double *T, double *dydt, ac_stream stream) {
+  if (ac_status s = check_cells(net, n_cells)) return s;
+  if (n_cells && (!y || !T || !dydt)) return fail(AC_EINVAL, "null y, T or dydt");
+  hipError_t e = ac::launch_rhs(net->d, log_alpha, n_cells, y, T, nullptr, dydt, hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_rhs launch");
+}
+
+ac_status ac_rhs_k(const ac_net *net, int64_t n_cells, const double *k, const double *y,
+                   double *dydt, ac_stream stream) {
+  if (ac_status s = check_cells(net, n_cells)) return s;
+  if (n_cells && (!k || !y || !dydt)) return fail(AC_EINVAL, "null k, y or dydt");
+  hipError_t e = ac::launch_rhs(net->d, nullptr, n_cells, y, nullptr, k, dydt, hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_rhs_k launch");
+}
+
+ac_status ac_jac(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *y,
+                 const double *T, double *jvals, ac_stream stream) {
+  if (ac_status s = check_cells(net, n_cells)) return s;
+  if (n_cells && (!y || !T || !jvals)) return fail(AC_EINVAL, "null y, T or jvals");
+  hipError_t e = ac::launch_jac(net->d, log_alpha, n_cells, y, T, jvals, hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_jac launch");
+}
+
+ac_status ac_vjp(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *y,
+                 const double *T, const double *v, double *gy, double *g_logalpha,
+                 ac_stream stream) {
+  if (ac_status s = check_cells(net, n_cells)) return s;
+  if (n_cells && (!y || !T || !v)) return fail(AC_EINVAL, "null y, T or v");
+  hipError_t e = ac::launch_vjp(net->d, log_alpha, n_cells, y, T, v, gy, g_logalpha,
+                                net->vjp_part, net->vjp_rows, hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_vjp launch");
+}
+
+}  // extern "C"

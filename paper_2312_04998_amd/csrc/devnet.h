@@ -1,0 +1,42 @@
+// Device views of a network, passed by value to kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ac {
+
+constexpr int LAYOUT_CSR = 0, LAYOUT_SELL = 1, LAYOUT_COO = 2;
+
+struct DSched {
+  int n_seg, n_chunk, n_item, n_slot, n_multi;
+  const int32_t *seg_out, *seg_chunk, *chunk_ptr, *chunk_dst, *multi_out, *multi_slot;
+  const uint32_t *items;
+  int sell_c, n_slice;
+  const int32_t *slice_ptr, *sell_chunk, *sell_len;
+  const uint32_t *sell_items;
+  const int32_t *coo_out;
+};
+
+struct DNet {
+  int ns, nr, nnz_j, layout;
+  const double *log_alpha, *beta, *gamma;
+  const uint32_t *rpair;       // reactant a | b << 16 (0xFFFF none)
+  const int32_t *s_col_ptr, *s_row, *s_cval;   // CCS of S
+  DSched rhs, jac, gy;
+};
+
+// Launchers (kernels_chem.hip). All enqueue on `stream`; return hipError_t.
+hipError_t launch_rates(const DNet &n, const double *log_alpha, int64_t n_cells, const double *T,
+                        double *k, hipStream_t stream);
+hipError_t launch_rhs(const DNet &n, const double *log_alpha, int64_t n_cells, const double *y,
+                      const double *T, const double *k, double *dydt, hipStream_t stream);
+hipError_t launch_jac(const DNet &n, const double *log_alpha, int64_t n_cells, const double *y,
+                      const double *T, double *jvals, hipStream_t stream);
+hipError_t launch_vjp(const DNet &n, const double *log_alpha, int64_t n_cells, const double *y,
+                      const double *T, const double *v, double *gy, double *g_logalpha,
+                      double *part, int part_rows, hipStream_t stream);
+size_t rhs_lds_bytes(const DNet &n);
+
+}  // namespace ac

@@ -169,7 +169,7 @@ def _make_species(n_species: int, rng: np.random.Generator,
         k = count.get(c, 0)
         count[c] = k + 1
         names.append(_name(c) + ("" if k == 0 else f"#{k}"))
-    is_surface = np.zeros(n_species, bool)
+    is_surface = np.zeros(n_gas, bool)
     if n_surface:
         # grain-surface twins: identical composition, distinct species
         neutral = [i for i in range(n_gas) if comp[i, 5] == 0 and comp[i, :5].sum() >= 1]
