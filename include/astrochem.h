@@ -98,8 +98,10 @@ typedef struct {
   int32_t layout;            /* ac_layout */
   int32_t ordering;          /* ac_ordering */
   int32_t chunk;             /* max nonzeros per row chunk; 0 = default (32) */
-  int32_t sell_c;            /* SELL slice width in chunks; 0 = default (64, one wavefront) */
+  int32_t sell_c;            /* SELL slice width in chunks: 0 or 64 (one wavefront) */
   int32_t sell_sigma;        /* SELL sorting window in chunks; 0 = default (whole matrix) */
+  int32_t block;             /* threads per workgroup of the chemistry kernels: 256, 512
+                                or 1024; 0 = default (512) */
 } ac_net_desc;
 
 typedef struct ac_net ac_net;
@@ -178,6 +180,80 @@ ac_status ac_jac(const ac_net *net, const double *log_alpha, int64_t n_cells, co
 ac_status ac_vjp(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *y,
                  const double *T, const double *v, double *gy, double *g_logalpha,
                  ac_stream stream);
+
+/* ------------------------------------------------ batched dense LU
+ * The Newton matrices of the implicit integrator are dense n x n (n =
+ * species), one per cell. A: [n_mat][n][lda] row-major DEVICE array,
+ * factored in place as P A = L U with unit lower L (partial pivoting, whole
+ * rows swapped, piv[k] = row exchanged with row k at step k); info[m] = 0 or
+ * 1 + index of the first exactly-zero pivot (info may be NULL). lda >= n. */
+ac_status ac_lu_factor(int32_t n, int32_t lda, int64_t n_mat, double *A, int32_t *piv,
+                       int32_t *info, ac_stream stream);
+/* Solves A x = b (trans = 0) or A^T x = b (trans = 1) in place in b
+ * [n_mat][n] with the factors of ac_lu_factor. */
+ac_status ac_lu_solve(int32_t n, int32_t lda, int64_t n_mat, const double *LU,
+                      const int32_t *piv, double *b, int32_t trans, ac_stream stream);
+
+/* ---------------------------------------------------------- integrator
+ * Variable-order (1..q_max <= 5) BDF in backward-difference form with a
+ * simplified Newton corrector on the dense matrix I - c J (the paper
+ * integrates every cell with the BDF code DLSODES, Sec. 3, and keeps T fixed
+ * during the chemistry update, Sec. 5). Rules, identical in the CPU oracle:
+ * error test on RMS(d / (atol + rtol |y|)) / (q+1) <= 1; step factor
+ * 0.9*9/(8+iters) * err^(-1/(q+1)) clamped to [0.2, 10]; order change to
+ * the best of q-1, q, q+1 after q+1 equal steps; at most 4 Newton
+ * iterations with a rate test; J refreshed once per attempt on Newton
+ * failure, then h halved; M refactored whenever h or q changes. */
+typedef struct {
+  double rtol;        /* > 0 */
+  double atol;        /* >= 0, in units of y */
+  double h0;          /* first step [s]; <= 0 selects it (Hairer-Norsett-Wanner) */
+  int32_t q_max;      /* 1..5; 1 is adaptive backward Euler */
+  int32_t max_steps;  /* accepted-step budget per cell */
+} ac_integ_opts;
+
+/* Per-cell counters written by the integrator ([n_cells][AC_NSTAT]). */
+enum { AC_STAT_STEPS = 0, AC_STAT_REJECT_ERR, AC_STAT_REJECT_NEWTON, AC_STAT_NEWTON_ITERS,
+       AC_STAT_JAC, AC_STAT_LU, AC_STAT_RHS, AC_STAT_Q_LAST, AC_NSTAT };
+
+/* Step-sequence record for replay and the adjoint: INIT (val = first step),
+ * RESCALE (difference array resampled for order q by factor val), STEP
+ * (accepted step of order q and size val). */
+typedef struct {
+  int32_t type;       /* 1 INIT, 2 RESCALE, 3 STEP */
+  int32_t q;
+  double val;
+} ac_event;
+
+typedef struct ac_ws ac_ws;
+
+/* Integrator workspace: one slot (Newton matrix, Jacobian values,
+ * difference array, coefficients: about 8 n^2 + 8 nnz_j + 64 n + 8 n_r
+ * bytes) per resident workgroup. n_slots = 0 uses every workgroup that
+ * fits on the device at once. All integrator scratch is allocated here. */
+ac_status ac_ws_create(const ac_net *net, int32_t n_slots, ac_ws **out);
+ac_status ac_ws_destroy(ac_ws *ws);
+ac_status ac_ws_info(const ac_ws *ws, int32_t *n_slots, int64_t *bytes);
+
+/* Integrates dy/dt = S R(y) from t = 0 to t_end for every cell, T held
+ * fixed per cell. y [n_cells][n_species] DEVICE, overwritten with y(t_end)
+ * (cells with AC_CELL_BADINPUT are left untouched); T [n_cells] DEVICE.
+ * cell_status [n_cells] and cell_stats [n_cells][AC_NSTAT] DEVICE (either
+ * may be NULL). tape [n_cells][tape_cap] and tape_len [n_cells] DEVICE
+ * record the step sequence when tape is not NULL (tape_len = -1 when a
+ * cell needs more than tape_cap events). Cells are handed to the
+ * workspace's persistent workgroups through a device queue; one workspace
+ * serves one stream at a time. */
+ac_status ac_integrate(ac_ws *ws, const double *log_alpha, int64_t n_cells, double *y,
+                       const double *T, double t_end, const ac_integ_opts *opts,
+                       int32_t *cell_status, int32_t *cell_stats, ac_event *tape,
+                       int32_t tape_cap, int32_t *tape_len, ac_stream stream);
+
+/* Same integrator, one cell per kernel launch, one workgroup, launches
+ * issued back to back from the host: the unbatched baseline. */
+ac_status ac_integrate_plain(ac_ws *ws, const double *log_alpha, int64_t n_cells, double *y,
+                             const double *T, double t_end, const ac_integ_opts *opts,
+                             int32_t *cell_status, int32_t *cell_stats, ac_stream stream);
 
 /* Status text and the calling thread's last error message (incl. HIP's). */
 const char *ac_status_string(ac_status s);

@@ -38,7 +38,8 @@ class NetDesc(C.Structure):
                 ("alpha", C.c_void_p), ("beta", C.c_void_p), ("gamma", C.c_void_p),
                 ("composition", C.c_void_p), ("n_elem", C.c_int32),
                 ("check_balance", C.c_int32), ("layout", C.c_int32), ("ordering", C.c_int32),
-                ("chunk", C.c_int32), ("sell_c", C.c_int32), ("sell_sigma", C.c_int32)]
+                ("chunk", C.c_int32), ("sell_c", C.c_int32), ("sell_sigma", C.c_int32),
+                ("block", C.c_int32)]
 
 
 def _load() -> C.CDLL:
@@ -68,10 +69,20 @@ def _load() -> C.CDLL:
     L.ac_status_string.restype = C.c_char_p
     L.ac_last_error.argtypes = [C.c_char_p, C.c_size_t]
     L.ac_last_error.restype = C.c_int
-    for name in ("ac_ws_create", "ac_ws_destroy", "ac_integrate", "ac_integrate_adjoint",
-                 "ac_integrate_plain"):
-        if hasattr(L, name):
-            getattr(L, name).restype = st
+    d = C.c_double
+    sig2 = {
+        "ac_lu_factor": [i32, i32, i64, vp, vp, vp, vp],
+        "ac_lu_solve": [i32, i32, i64, vp, vp, vp, i32, vp],
+        "ac_ws_create": [vp, i32, vp],
+        "ac_ws_destroy": [vp],
+        "ac_ws_info": [vp, vp, vp],
+        "ac_integrate": [vp, vp, i64, vp, vp, d, vp, vp, vp, vp, i32, vp, vp],
+        "ac_integrate_plain": [vp, vp, i64, vp, vp, d, vp, vp, vp, vp],
+    }
+    for name, args in sig2.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = st
     return L
 
 
@@ -117,13 +128,23 @@ def _check_dev(t, shape, name: str):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
 
 
+class IntegOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h0", C.c_double),
+                ("q_max", C.c_int32), ("max_steps", C.c_int32)]
+
+
+EVENT_DTYPE = np.dtype([("type", np.int32), ("q", np.int32), ("val", np.float64)])
+STAT_NAMES = ("steps", "reject_err", "reject_newton", "newton_it", "jac", "lu", "rhs", "q_last")
+NSTAT = len(STAT_NAMES)
+
+
 class Network:
     """Owns an ac_net handle built from a reaction list (arrays as in
     synthnet.Network: reactants [nr,2], products [nr,4], alpha/beta/gamma)."""
 
     def __init__(self, reactants, products, alpha, beta, gamma, composition=None,
-                 layout: str = "csr", ordering: str = "natural", chunk: int = 0, sell_c: int = 0,
-                 sell_sigma: int = 0, check_balance: bool = False):
+                 layout: str = "sell", ordering: str = "nnz", chunk: int = 0, sell_c: int = 0,
+                 sell_sigma: int = 0, check_balance: bool = False, block: int = 0):
         self._rea = np.ascontiguousarray(reactants, np.int32)
         self._pro = np.ascontiguousarray(products, np.int32)
         self._a = np.ascontiguousarray(alpha, np.float64)
@@ -139,7 +160,7 @@ class Network:
         d = NetDesc(self.n_species, self.n_reactions, _ptr(self._rea), _ptr(self._pro),
                     _ptr(self._a), _ptr(self._b), _ptr(self._g), _ptr(self._comp),
                     0 if self._comp is None else self._comp.shape[1], int(check_balance),
-                    LAYOUTS[layout], ORDERINGS[ordering], chunk, sell_c, sell_sigma)
+                    LAYOUTS[layout], ORDERINGS[ordering], chunk, sell_c, sell_sigma, block)
         h = C.c_void_p()
         check(lib.ac_net_create(C.byref(d), C.byref(h)), "ac_net_create")
         self.handle = h
@@ -288,3 +309,82 @@ def ac_sparse_format(dense, fmt: int, width: int = 0):
                                _ptr(idx2), _ptr(ptr)), "ac_sparse_format")
     n = cap.value
     return val[:n], idx[:n], idx2[:n], ptr
+
+
+# ---------------------------------------------------------------- dense LU
+
+def ac_lu_factor(A, piv, info=None, lda=None, stream=None):
+    """A: [n_mat, n, lda] float64 device tensor (in place), piv: int32 [n_mat, n]."""
+    n_mat, n = A.shape[0], A.shape[1]
+    lda = A.shape[2] if lda is None else lda
+    check(lib.ac_lu_factor(n, lda, n_mat, _ptr(A), _ptr(piv), _ptr(info), _stream(stream)),
+          "ac_lu_factor")
+
+
+def ac_lu_solve(LU, piv, b, trans=False, stream=None):
+    n_mat, n, lda = LU.shape
+    check(lib.ac_lu_solve(n, lda, n_mat, _ptr(LU), _ptr(piv), _ptr(b), int(trans), _stream(stream)),
+          "ac_lu_solve")
+
+
+# -------------------------------------------------------------- integrator
+
+class Workspace:
+    """Owns an ac_ws (integrator slots) for one network."""
+
+    def __init__(self, net: Network, n_slots: int = 0):
+        self.net = net
+        h = C.c_void_p()
+        check(lib.ac_ws_create(net.handle, int(n_slots), C.byref(h)), "ac_ws_create")
+        self.handle = h
+        ns, nb = C.c_int32(), C.c_int64()
+        check(lib.ac_ws_info(h, C.byref(ns), C.byref(nb)), "ac_ws_info")
+        self.n_slots, self.bytes = ns.value, nb.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.ac_ws_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def integrate(self, y, T, t_end, rtol=1e-6, atol=1e-20, q_max=5, max_steps=100000, h0=0.0,
+                  log_alpha=None, tape_cap=0, plain=False, stream=None):
+        """Integrates y (device, in place) to t_end. Returns dict of device
+        tensors: status [n], stats [n, NSTAT] and, with tape_cap > 0, the
+        recorded steps (tape [n, tape_cap] of EVENT_DTYPE bytes, tape_len)."""
+        import torch
+        n = T.shape[0]
+        _check_dev(T, (n,), "T")
+        _check_dev(y, (n, self.net.n_species), "y")
+        if log_alpha is not None:
+            _check_dev(log_alpha, (self.net.n_reactions,), "log_alpha")
+        dev = y.device
+        status = torch.empty(n, dtype=torch.int32, device=dev)
+        stats = torch.empty((n, NSTAT), dtype=torch.int32, device=dev)
+        o = IntegOpts(float(rtol), float(atol), float(h0), int(q_max), int(max_steps))
+        out = {"status": status, "stats": stats}
+        if plain:
+            check(lib.ac_integrate_plain(self.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T),
+                                         float(t_end), C.byref(o), _ptr(status), _ptr(stats),
+                                         _stream(stream)), "ac_integrate_plain")
+            return out
+        tape = tlen = None
+        if tape_cap > 0:
+            tape = torch.empty((n, tape_cap, 2), dtype=torch.float64, device=dev)   # 16-byte events
+            tlen = torch.empty(n, dtype=torch.int32, device=dev)
+            out["tape"], out["tape_len"] = tape, tlen
+        check(lib.ac_integrate(self.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T), float(t_end),
+                               C.byref(o), _ptr(status), _ptr(stats), _ptr(tape), int(tape_cap),
+                               _ptr(tlen), _stream(stream)), "ac_integrate")
+        return out
+
+
+def tape_to_numpy(tape_tensor):
+    """Device tape tensor -> numpy structured array of EVENT_DTYPE."""
+    raw = tape_tensor.cpu().numpy()
+    return raw.view(np.uint8).reshape(raw.shape[0], raw.shape[1], 16).copy().view(EVENT_DTYPE)[..., 0]

@@ -2,12 +2,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "../../include/astrochem.h"
+#include "devbdf.h"
 #include "devnet.h"
 #include "netbuild.h"
 
@@ -131,6 +134,8 @@ int ac_last_error(char *buf, size_t n) {
 ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
   if (!desc || !out) return fail(AC_EINVAL, "null argument");
   *out = nullptr;
+  if (desc->block != 0 && desc->block != 256 && desc->block != 512 && desc->block != 1024)
+    return fail(AC_EINVAL, "block must be 0, 256, 512 or 1024");
   ac_net *net = new (std::nothrow) ac_net();
   if (!net) return fail(AC_ENOMEM, "host allocation failed");
   int code = 0;
@@ -151,9 +156,12 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
   const ac::HostNet &H = net->host;
   Packer p;
   const size_t o_la = p.add(H.log_alpha), o_be = p.add(H.beta), o_ga = p.add(H.gamma);
-  const size_t o_rp = p.add(H.rpair);
+  const size_t o_rp = p.add(H.rpair), o_rx = p.add(H.rxpack);
   const size_t o_cp = p.add(H.s_col_ptr), o_cr = p.add(H.s_row), o_cv = p.add(H.s_cval);
   const SchedOff o_rhs = add_sched(p, H.rhs), o_jac = add_sched(p, H.jac), o_gy = add_sched(p, H.gy);
+  const SchedOff o_jt = add_sched(p, H.jtail);
+  const size_t o_h0 = p.add(H.jhead0), o_h1 = p.add(H.jhead1), o_td = p.add(H.jtaildesc);
+  const size_t o_er = p.add(H.jent_row), o_ec = p.add(H.j_col);
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();
@@ -185,16 +193,24 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
   d.nr = H.nr;
   d.nnz_j = int(H.j_col.size());
   d.layout = H.layout;
+  d.block = desc->block ? desc->block : 512;
   d.log_alpha = at<double>(b, o_la);
   d.beta = at<double>(b, o_be);
   d.gamma = at<double>(b, o_ga);
   d.rpair = at<uint32_t>(b, o_rp);
+  d.rxpack = at<uint4>(b, o_rx);
   d.s_col_ptr = at<int32_t>(b, o_cp);
   d.s_row = at<int32_t>(b, o_cr);
   d.s_cval = at<int32_t>(b, o_cv);
   d.rhs = dev_sched(b, H.rhs, o_rhs);
   d.jac = dev_sched(b, H.jac, o_jac);
   d.gy = dev_sched(b, H.gy, o_gy);
+  d.jtail = dev_sched(b, H.jtail, o_jt);
+  d.jhead0 = at<uint32_t>(b, o_h0);
+  d.jhead1 = at<uint32_t>(b, o_h1);
+  d.jtaildesc = at<uint32_t>(b, o_td);
+  d.jent_row = at<int32_t>(b, o_er);
+  d.jent_col = at<int32_t>(b, o_ec);
   *out = net;
   return AC_OK;
 }
@@ -365,6 +381,167 @@ ac_status ac_vjp(const ac_net *net, const double *log_alpha, int64_t n_cells, co
   hipError_t e = ac::launch_vjp(net->d, log_alpha, n_cells, y, T, v, gy, g_logalpha,
                                 net->vjp_part, net->vjp_rows, hipStream_t(stream));
   return e == hipSuccess ? AC_OK : hip_fail(e, "ac_vjp launch");
+}
+
+// ---------------------------------------------------------- dense LU
+
+ac_status ac_lu_factor(int32_t n, int32_t lda, int64_t n_mat, double *A, int32_t *piv,
+                       int32_t *info, ac_stream stream) {
+  if (n <= 0 || lda < n || n_mat < 0) return fail(AC_EINVAL, "need n > 0, lda >= n, n_mat >= 0");
+  if (n_mat && (!A || !piv)) return fail(AC_EINVAL, "null A or piv");
+  hipError_t e = ac::launch_lu_factor(n, lda, n_mat, A, piv, info, hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_lu_factor launch");
+}
+
+ac_status ac_lu_solve(int32_t n, int32_t lda, int64_t n_mat, const double *LU,
+                      const int32_t *piv, double *b, int32_t trans, ac_stream stream) {
+  if (n <= 0 || lda < n || n_mat < 0) return fail(AC_EINVAL, "need n > 0, lda >= n, n_mat >= 0");
+  if (n_mat && (!LU || !piv || !b)) return fail(AC_EINVAL, "null LU, piv or b");
+  if (sizeof(double) * (size_t(n) + 32 * 32) > 160 * 1024)
+    return fail(AC_ELIMIT, "n too large for an LDS-resident right-hand side");
+  hipError_t e = ac::launch_lu_solve(n, lda, n_mat, LU, piv, b, trans, hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_lu_solve launch");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------- integrator
+
+struct ac_ws {
+  const ac_net *net = nullptr;
+  int n_slots = 0;
+  size_t bytes = 0;
+  void *buf = nullptr;
+  unsigned *queue = nullptr;
+  ac::WsView W{};
+};
+
+extern "C" {
+
+ac_status ac_ws_create(const ac_net *net, int32_t n_slots, ac_ws **out) {
+  if (!net || !out) return fail(AC_EINVAL, "null argument");
+  *out = nullptr;
+  if (!net->dbuf) return fail(AC_EHIP, "network has no device copy (no GPU at creation)");
+  if (n_slots < 0) return fail(AC_EINVAL, "n_slots < 0");
+  if (ac::bdf_lds_bytes(net->d) > 160 * 1024)
+    return fail(AC_ELIMIT, "network too large for the integrator's LDS working set");
+  const int resident = ac::bdf_resident_blocks(net->d);
+  ac_ws *ws = new (std::nothrow) ac_ws();
+  if (!ws) return fail(AC_ENOMEM, "host allocation failed");
+  ws->net = net;
+  ws->n_slots = n_slots ? n_slots : resident;
+  const int ns = net->d.ns, nr = net->d.nr, nnz = net->d.nnz_j;
+  const int lda = (ns + 15) / 16 * 16;
+  auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t m_b = r256(sizeof(double) * size_t(ns) * lda);
+  const size_t j_b = r256(sizeof(double) * size_t(nnz));
+  const size_t t_b = r256(sizeof(double) * size_t(std::max(1, net->host.jtail.n_slot)));
+  const size_t d_b = r256(sizeof(double) * size_t(8) * ns);
+  const size_t k_b = r256(sizeof(double) * size_t(nr));
+  const size_t p_b = r256(sizeof(int) * size_t(ns));
+  const size_t per = m_b + j_b + t_b + d_b + k_b + p_b;
+  ws->bytes = per * size_t(ws->n_slots) + 256;
+  hipError_t e = hipMalloc(&ws->buf, ws->bytes);
+  if (e != hipSuccess) {
+    delete ws;
+    return hip_fail(e, "hipMalloc(workspace)");
+  }
+  char *b = static_cast<char *>(ws->buf);
+  const size_t S = size_t(ws->n_slots);
+  ac::WsView &W = ws->W;
+  W.M = reinterpret_cast<double *>(b);
+  b += m_b * S;
+  W.J = reinterpret_cast<double *>(b);
+  b += j_b * S;
+  W.tail = reinterpret_cast<double *>(b);
+  b += t_b * S;
+  W.D = reinterpret_cast<double *>(b);
+  b += d_b * S;
+  W.k = reinterpret_cast<double *>(b);
+  b += k_b * S;
+  W.piv = reinterpret_cast<int *>(b);
+  b += p_b * S;
+  ws->queue = reinterpret_cast<unsigned *>(b);
+  W.m_stride = m_b / sizeof(double);
+  W.j_stride = j_b / sizeof(double);
+  W.tail_stride = t_b / sizeof(double);
+  W.d_stride = d_b / sizeof(double);
+  W.k_stride = k_b / sizeof(double);
+  W.piv_stride = p_b / sizeof(int);
+  W.lda = lda;
+  // Debug aid: ASTROCHEM_POISON_WS=1 fills the floating-point slot regions
+  // with NaN so any read of state a cell did not write itself shows up.
+  const char *poison = std::getenv("ASTROCHEM_POISON_WS");
+  if (poison && poison[0] == '1') {
+    const size_t fp_bytes = (m_b + j_b + t_b + d_b + k_b) * S;
+    e = hipMemset(ws->buf, 0xFF, fp_bytes);
+    if (e == hipSuccess) e = hipMemset(W.piv, 0, p_b * S);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      hipFree(ws->buf);
+      delete ws;
+      return hip_fail(e, "workspace poison fill");
+    }
+  }
+  *out = ws;
+  return AC_OK;
+}
+
+ac_status ac_ws_destroy(ac_ws *ws) {
+  if (!ws) return AC_OK;
+  hipFree(ws->buf);
+  delete ws;
+  return AC_OK;
+}
+
+ac_status ac_ws_info(const ac_ws *ws, int32_t *n_slots, int64_t *bytes) {
+  if (!ws) return fail(AC_EINVAL, "null workspace");
+  if (n_slots) *n_slots = ws->n_slots;
+  if (bytes) *bytes = int64_t(ws->bytes);
+  return AC_OK;
+}
+
+static ac_status integ_args(ac_ws *ws, int64_t n_cells, const double *y, const double *T,
+                            double t_end, const ac_integ_opts *o) {
+  if (!ws || !o) return fail(AC_EINVAL, "null workspace or options");
+  if (n_cells < 0) return fail(AC_EINVAL, "n_cells < 0");
+  if (n_cells && (!y || !T)) return fail(AC_EINVAL, "null y or T");
+  if (!(o->rtol > 0.0) || !(o->atol >= 0.0)) return fail(AC_EINVAL, "need rtol > 0, atol >= 0");
+  if (o->q_max < 1 || o->q_max > 5) return fail(AC_EINVAL, "q_max must be 1..5");
+  if (o->max_steps < 1) return fail(AC_EINVAL, "max_steps must be >= 1");
+  if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(AC_EINVAL, "t_end must be finite and >= 0");
+  return AC_OK;
+}
+
+ac_status ac_integrate(ac_ws *ws, const double *log_alpha, int64_t n_cells, double *y,
+                       const double *T, double t_end, const ac_integ_opts *opts,
+                       int32_t *cell_status, int32_t *cell_stats, ac_event *tape,
+                       int32_t tape_cap, int32_t *tape_len, ac_stream stream) {
+  if (ac_status s = integ_args(ws, n_cells, y, T, t_end, opts)) return s;
+  if (tape && (tape_cap <= 0 || !tape_len)) return fail(AC_EINVAL, "tape needs tape_cap > 0 and tape_len");
+  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, t_end, opts->q_max, opts->max_steps};
+  ac::CellOut out{cell_status, cell_stats};
+  ac::TapeView tv{reinterpret_cast<ac::AcEvent *>(tape), tape ? tape_len : nullptr, tape ? tape_cap : 0};
+  hipError_t e = ac::launch_bdf(ws->net->d, log_alpha, n_cells, y, T, P, out, tv, ws->W, ws->queue,
+                                ws->n_slots, hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_integrate launch");
+}
+
+ac_status ac_integrate_plain(ac_ws *ws, const double *log_alpha, int64_t n_cells, double *y,
+                             const double *T, double t_end, const ac_integ_opts *opts,
+                             int32_t *cell_status, int32_t *cell_stats, ac_stream stream) {
+  if (ac_status s = integ_args(ws, n_cells, y, T, t_end, opts)) return s;
+  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, t_end, opts->q_max, opts->max_steps};
+  const int ns = ws->net->d.ns;
+  for (int64_t c = 0; c < n_cells; ++c) {
+    ac::CellOut out{cell_status ? cell_status + c : nullptr,
+                    cell_stats ? cell_stats + c * AC_NSTAT : nullptr};
+    ac::TapeView tv{nullptr, nullptr, 0};
+    hipError_t e = ac::launch_bdf(ws->net->d, log_alpha, 1, y + c * ns, T + c, P, out, tv, ws->W,
+                                  nullptr, 1, hipStream_t(stream));
+    if (e != hipSuccess) return hip_fail(e, "ac_integrate_plain launch");
+  }
+  return AC_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,58 @@
+// Integrator data shared by the host API and the BDF kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/astrochem.h"
+#include "devnet.h"
+
+namespace ac {
+
+constexpr int BDF_NT = 256;   // threads per integrator workgroup (4 wavefronts)
+
+// per-cell counters, same order as the public ac_stat enum
+enum { ST_STEPS = 0, ST_REJ_ERR, ST_REJ_NEWTON, ST_NEWTON, ST_JAC, ST_LU, ST_RHS, ST_QLAST, ST_N };
+enum { EV_INIT = 1, EV_RESCALE = 2, EV_STEP = 3 };
+
+struct AcEvent {
+  int32_t type, q;
+  double val;
+};
+
+struct BdfParams {
+  double rtol, atol, h0, t_end;
+  int q_max, max_steps;
+};
+
+struct CellOut {
+  int32_t *status;   // [n_cells] or null
+  int32_t *stats;    // [n_cells][ST_N] or null
+};
+
+struct TapeView {
+  AcEvent *ev;       // [n_cells][cap] or null
+  int32_t *len;      // [n_cells] or null
+  int cap;
+};
+
+// Global workspace slots (one per resident workgroup).
+struct WsView {
+  double *M, *J, *tail, *D, *k;
+  int *piv;
+  size_t m_stride, j_stride, tail_stride, d_stride, k_stride, piv_stride;
+  int lda;
+};
+
+size_t bdf_lds_bytes(const DNet &n);
+int bdf_resident_blocks(const DNet &n);
+hipError_t launch_bdf(const DNet &n, const double *la, int64_t n_cells, double *y, const double *T,
+                      const BdfParams &P, const CellOut &out, const TapeView &tv, const WsView &W,
+                      unsigned *queue, int grid, hipStream_t st);
+hipError_t launch_lu_factor(int n, int lda, int64_t nmat, double *A, int *piv, int *info,
+                            hipStream_t st);
+hipError_t launch_lu_solve(int n, int lda, int64_t nmat, const double *LU, const int *piv,
+                           double *b, int trans, hipStream_t st);
+
+}  // namespace ac

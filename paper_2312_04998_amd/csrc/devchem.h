@@ -1,0 +1,180 @@
+// Device helpers shared by the chemistry and integrator kernels: packed
+// term evaluation, chunked gather sums over a schedule, reaction records.
+#pragma once
+
+#include "devnet.h"
+
+namespace ac {
+
+constexpr int SELL_C = 64;     // slice width of every SELL schedule (one wavefront)
+constexpr int UNROLL = 8;      // terms in flight per lane
+constexpr uint32_t PAD_ITEM = 2047u << 16;   // coef 0, no density factor
+
+// value of one packed term: coef * A[j] * (b == NONE ? 1 : y[b])
+__device__ __forceinline__ double term(uint32_t it, const double *__restrict__ A,
+                                       const double *__restrict__ ys) {
+  const int j = int(it & 0xFFFFu);
+  const int b = int((it >> 16) & 2047u);
+  const int coef = int32_t(it) >> 27;
+  double v = double(coef) * A[j];
+  if (b != 2047) v *= ys[b];
+  return v;
+}
+
+template <bool STREAM>
+__device__ __forceinline__ void put(double *p, double v) {
+  if (STREAM) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Chunk sums of a schedule: single-chunk segments go straight to out,
+// split segments leave partials in `part` for segsum_finish. Sums are
+// left to right with plain (uncontracted) adds, so CSR and SELL give the
+// same bits. SELL lanes of a slice loop to the slice width (wave-uniform)
+// with UNROLL term loads issued before they are consumed; IDENT marks a
+// schedule whose positions are its chunk ids (sigma = 1).
+template <int NT, int LAYOUT, bool IDENT, bool STREAM>
+__device__ __forceinline__ void segsum_chunks(const DSched &s, const double *__restrict__ A,
+                                              const double *__restrict__ ys, double *part,
+                                              double *__restrict__ out) {
+  if (LAYOUT == LAYOUT_SELL) {
+    const int npos = s.n_slice * SELL_C;
+    for (int pos = threadIdx.x; pos < npos; pos += NT) {
+      const int ch = IDENT ? (pos < s.n_chunk ? pos : -1) : s.sell_chunk[pos];
+      const int sl = pos / SELL_C;
+      const int base = s.slice_ptr[sl];
+      const int width = (s.slice_ptr[sl + 1] - base) / SELL_C;
+      const int len = s.sell_len[pos];
+      const uint32_t *it = s.sell_items + base + (pos - sl * SELL_C);
+      double acc = 0.0;
+      for (int k0 = 0; k0 < width; k0 += UNROLL) {
+        uint32_t v[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) v[u] = (k0 + u < width) ? it[(k0 + u) * SELL_C] : PAD_ITEM;
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const double t = term(v[u], A, ys);
+          if (k0 + u < len) acc = __dadd_rn(acc, t);
+        }
+      }
+      if (ch >= 0) {
+        const int d = s.chunk_dst[ch];
+        if (d >= 0) put<STREAM>(out + d, acc);
+        else part[-1 - d] = acc;
+      }
+    }
+  } else {
+    for (int ch = threadIdx.x; ch < s.n_chunk; ch += NT) {
+      double acc = 0.0;
+      const int p0 = s.chunk_ptr[ch], p1 = s.chunk_ptr[ch + 1];
+      for (int k0 = p0; k0 < p1; k0 += UNROLL) {
+        uint32_t v[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) v[u] = (k0 + u < p1) ? s.items[k0 + u] : PAD_ITEM;
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const double t = term(v[u], A, ys);
+          if (k0 + u < p1) acc = __dadd_rn(acc, t);
+        }
+      }
+      const int d = s.chunk_dst[ch];
+      if (d >= 0) put<STREAM>(out + d, acc);
+      else part[-1 - d] = acc;
+    }
+  }
+}
+
+template <int NT, bool STREAM>
+__device__ __forceinline__ void segsum_finish(const DSched &s, const double *part,
+                                              double *__restrict__ out) {
+  for (int m = threadIdx.x; m < s.n_multi; m += NT) {
+    const int q0 = s.multi_slot[m], q1 = s.multi_slot[m + 1];
+    double acc = part[q0];
+    for (int q = q0 + 1; q < q1; ++q) acc = __dadd_rn(acc, part[q]);
+    put<STREAM>(out + s.multi_out[m], acc);
+  }
+}
+
+// Full segmented sum (partials in LDS, so a barrier sits in between).
+template <int NT, int LAYOUT>
+__device__ __forceinline__ void segsum(const DSched &s, const double *A, const double *ys,
+                                       double *part, double *out) {
+  if (LAYOUT == LAYOUT_COO) {
+    // scatter with LDS atomics into a per-cell accumulator (order varies)
+    for (int i = threadIdx.x; i < s.n_seg; i += NT) part[i] = 0.0;
+    __syncthreads();
+    for (int p = threadIdx.x; p < s.n_item; p += NT)
+      atomicAdd(&part[s.coo_out[p]], term(s.items[p], A, ys));
+    __syncthreads();
+    for (int i = threadIdx.x; i < s.n_seg; i += NT) out[i] = part[i];
+    return;
+  }
+  segsum_chunks<NT, LAYOUT, false, false>(s, A, ys, part, out);
+  __syncthreads();
+  segsum_finish<NT, false>(s, part, out);
+}
+
+template <int NT>
+__device__ __forceinline__ void load_cell(const double *__restrict__ src, double *dst, int n) {
+  for (int i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
+}
+
+// Reaction record: ln alpha, beta, gamma, reactant pair (two 16-byte loads).
+struct Rx {
+  double la, beta, gamma;
+  uint32_t pair;
+};
+
+__device__ __forceinline__ Rx load_rx(const DNet &n, int j) {
+  const uint4 a = n.rxpack[4 * j], b = n.rxpack[4 * j + 1];
+  Rx r;
+  r.la = __hiloint2double(int(a.y), int(a.x));
+  r.beta = __hiloint2double(int(a.w), int(a.z));
+  r.gamma = __hiloint2double(int(b.y), int(b.x));
+  r.pair = b.z;
+  return r;
+}
+
+// k_j = exp(ln alpha_j + beta_j ln(T/300) - gamma_j / T)
+__device__ __forceinline__ double kooij(double la, double beta, double gamma, double L,
+                                        double invT) {
+  return exp(la + beta * L - gamma * invT);
+}
+
+__device__ __forceinline__ double reaction_rate(uint32_t pair, double k, const double *ys) {
+  double r = k * ys[pair & 0xFFFFu];
+  const uint32_t b = pair >> 16;
+  if (b != 0xFFFFu) r *= ys[b];
+  return r;
+}
+
+// For every reaction j of this thread (j = tid + m*NT), with RXU records
+// loaded before any is used: fn(j, k_j, pair).
+constexpr int RXU = 4;
+template <int NT, typename F>
+__device__ __forceinline__ void for_reactions(const DNet &n, const double *__restrict__ la_over,
+                                              double L, double invT, F fn) {
+  for (int j0 = threadIdx.x; j0 < n.nr; j0 += RXU * NT) {
+    Rx r[RXU];
+#pragma unroll
+    for (int u = 0; u < RXU; ++u) {
+      const int j = j0 + u * NT;
+      if (j < n.nr) {
+        r[u] = load_rx(n, j);
+        if (la_over) r[u].la = la_over[j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RXU; ++u) {
+      const int j = j0 + u * NT;
+      if (j < n.nr) fn(j, kooij(r[u].la, r[u].beta, r[u].gamma, L, invT), r[u].pair);
+    }
+  }
+}
+
+__device__ __forceinline__ void cell_temperature(double Tc, double &L, double &invT) {
+  L = log(Tc / 300.0);
+  invT = 1.0 / Tc;
+}
+
+}  // namespace ac

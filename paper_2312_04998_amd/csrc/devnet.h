@@ -20,11 +20,14 @@ struct DSched {
 };
 
 struct DNet {
-  int ns, nr, nnz_j, layout;
+  int ns, nr, nnz_j, layout, block;
   const double *log_alpha, *beta, *gamma;
   const uint32_t *rpair;       // reactant a | b << 16 (0xFFFF none)
+  const uint4 *rxpack;         // 4 x uint4 per reaction: (la, beta) (gamma, rpair) (S column)
   const int32_t *s_col_ptr, *s_row, *s_cval;   // CCS of S
-  DSched rhs, jac, gy;
+  DSched rhs, jac, gy, jtail;
+  const uint32_t *jhead0, *jhead1, *jtaildesc;
+  const int32_t *jent_row, *jent_col;   // row and column of every pattern entry
 };
 
 // Launchers (kernels_chem.hip). All enqueue on `stream`; return hipError_t.

@@ -1,0 +1,530 @@
+// Batched stiff integrator for gfx950: variable-order (1..5) BDF in
+// backward-difference form with a simplified Newton corrector on the dense
+// Newton matrix I - c J, factored on the FP64 matrix cores.
+//
+// The paper integrates every cell with DLSODES (Sec. 3) and precomputes the
+// rate coefficients outside the solver; here one persistent workgroup
+// integrates one cell at a time, pulling cell indices from a device queue
+// so cells with many steps do not hold up the others. The coefficients are
+// computed once per cell; every RHS, Jacobian, factorisation and solve of
+// the cell then runs inside the same workgroup. Per-slot state (Newton
+// matrix, Jacobian values, difference array, coefficients) lives in a
+// global workspace slot; vectors of one cell live in LDS.
+//
+// Step, order and Newton rules (identical on the CPU oracle):
+//   gamma_q = sum_{m<=q} 1/m, alpha_q = gamma_q, error constant 1/(q+1)
+//   corrector d - c f(y_pred + d) + psi = 0, c = h/alpha_q,
+//     psi = sum_{m=1..q} gamma_m D_m / alpha_q; simplified Newton with
+//     M = I - c J, <= 4 iterations, convergence-rate test with tolerance
+//     max(10 eps/rtol, min(0.03, sqrt(rtol)))
+//   Newton failure: refresh J at y_pred once per attempt, then halve h
+//   error test: RMS of d/(atol + rtol|y_new|)/(q+1) <= 1; step factor
+//     safety * err^(-1/(q+1)) in [0.2, 10], safety = 0.9*9/(8 + iterations)
+//   order change after q+1 equal steps, to the best of q-1, q, q+1
+//   M refactored whenever c changes; J refreshed only on Newton failure.
+#include "devchem.h"
+#include "devla.h"
+#include "devbdf.h"
+
+namespace ac {
+
+constexpr int QMAX = 5, NDROW = QMAX + 3, NEWTON_MAXITER = 4;
+constexpr double MIN_FACTOR = 0.2, MAX_FACTOR = 10.0;
+
+// gamma_q = sum_{m=1..q} 1/m (summed in increasing m), alpha_q = gamma_q,
+// error constant 1/(q+1)
+__device__ __forceinline__ double bdf_gamma(int q) {
+  double g = 0.0;
+  for (int m = 1; m <= q; ++m) g += 1.0 / m;
+  return g;
+}
+__device__ __forceinline__ double bdf_errc(int q) { return 1.0 / (q + 1); }
+
+__device__ __forceinline__ double pow_neg(double x, double e) {
+  return x == 0.0 ? INFINITY : pow(x, -e);
+}
+
+// Per-workgroup view of one cell's work.
+struct CellCtx {
+  const DNet *n;
+  double *kg;      // rate coefficients (slot, global)
+  double *Jg;      // Jacobian values (slot, global)
+  double *tailp;   // Jacobian tail partials (slot, global)
+  double *M;       // Newton matrix / LU (slot, global)
+  int *piv;        // pivots (slot, global)
+  double *D;       // difference array [NDROW][ns] (slot, global)
+  int lda;
+  double *rs, *part, *blk, *red;   // LDS scratch
+  int *redi;
+  int cnt[ST_N];   // per-cell counters (identical on every thread)
+};
+
+template <int NT>
+__device__ __forceinline__ double wg_rms(const double *x, double mul, const double *scale, int n,
+                                         double *red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const double v = mul * x[i] / scale[i];
+    s += v * v;
+  }
+  return sqrt(wg_sum<NT>(s, red) / n);
+}
+
+template <int NT>
+__device__ __forceinline__ bool wg_any(bool b, double *red) {
+  return wg_sum<NT>(b ? 1.0 : 0.0, red) > 0.0;
+}
+
+// f = S R(y) with the cell's coefficients; y and f in LDS.
+template <int NT>
+__device__ void cell_rhs(CellCtx &cx, const double *y, double *f) {
+  const DNet &n = *cx.n;
+  for (int j = threadIdx.x; j < n.nr; j += NT) cx.rs[j] = reaction_rate(n.rpair[j], cx.kg[j], y);
+  __syncthreads();
+  segsum_chunks<NT, LAYOUT_SELL, false, false>(n.rhs, cx.rs, y, cx.part, f);
+  __syncthreads();
+  segsum_finish<NT, false>(n.rhs, cx.part, f);
+  __syncthreads();
+  cx.cnt[ST_RHS]++;
+}
+
+// Jacobian values on the pattern at y (LDS) into the slot.
+template <int NT>
+__device__ void cell_jac(CellCtx &cx, const double *y) {
+  const DNet &n = *cx.n;
+  segsum_chunks<NT, LAYOUT_SELL, true, false>(n.jtail, cx.kg, y, cx.tailp, nullptr);
+  __syncthreads();
+  for (int e = threadIdx.x; e < n.nnz_j; e += NT) {
+    double acc = term(n.jhead0[e], cx.kg, y);
+    acc = __dadd_rn(acc, term(n.jhead1[e], cx.kg, y));
+    const uint32_t td = n.jtaildesc[e];
+    const int q0 = int(td >> 8), nq = int(td & 255u);
+    for (int q = 0; q < nq; ++q) acc = __dadd_rn(acc, cx.tailp[q0 + q]);
+    cx.Jg[e] = acc;
+  }
+  __syncthreads();
+  cx.cnt[ST_JAC]++;
+}
+
+// M = I - c J (dense, row-major, lda) from the pattern values, then LU.
+template <int NT>
+__device__ void cell_factor(CellCtx &cx, double c) {
+  const DNet &n = *cx.n;
+  const int ns = n.ns, lda = cx.lda;
+  for (int e = threadIdx.x; e < ns * lda; e += NT) {
+    const int i = e / lda, a = e - i * lda;
+    cx.M[e] = (i == a) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n.nnz_j; e += NT) {
+    const int i = n.jent_row[e], a = n.jent_col[e];
+    cx.M[size_t(i) * lda + a] = (i == a ? 1.0 : 0.0) - c * cx.Jg[e];
+  }
+  __syncthreads();
+  wg_lu<NT>(cx.M, lda, ns, cx.piv, cx.red, cx.redi);
+  cx.cnt[ST_LU]++;
+}
+
+// Resample D[0..q] for a step change by `factor` (Shampine & Reichelt
+// 1997): D <- (R(factor) U)^T D with U = R(1).
+template <int NT>
+__device__ void rescale_diffs(CellCtx &cx, int q, double factor, int ns) {
+  constexpr int W = QMAX + 1;
+  double *RU = cx.red + 8, *R = RU + W * W, *U = R + W * W;   // LDS
+  if (threadIdx.x == 0) {
+    for (int j = 0; j <= q; ++j) {
+      R[j] = 1.0;
+      U[j] = 1.0;
+    }
+    for (int i = 1; i <= q; ++i) {
+      R[i * W] = 0.0;
+      U[i * W] = 0.0;
+      for (int j = 1; j <= q; ++j) {
+        R[i * W + j] = R[(i - 1) * W + j] * ((i - 1 - factor * j) / i);
+        U[i * W + j] = U[(i - 1) * W + j] * ((i - 1 - 1.0 * j) / i);
+      }
+    }
+    for (int i = 0; i <= q; ++i)
+      for (int j = 0; j <= q; ++j) {
+        double s = 0.0;
+        for (int m = 0; m <= q; ++m) s += R[i * W + m] * U[m * W + j];
+        RU[i * W + j] = s;
+      }
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < ns; x += NT) {
+    double old[QMAX + 1];
+#pragma unroll
+    for (int i = 0; i <= QMAX; ++i) old[i] = i <= q ? cx.D[size_t(i) * ns + x] : 0.0;
+#pragma unroll
+    for (int kk = 0; kk <= QMAX; ++kk) {
+      if (kk > q) break;
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i <= QMAX; ++i)
+        if (i <= q) s += RU[i * W + kk] * old[i];
+      cx.D[size_t(kk) * ns + x] = s;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void tape_put(const TapeView &tv, int64_t cell, int &len, int type,
+                                         int q, double val) {
+  if (!tv.ev) return;
+  if (threadIdx.x == 0 && len < tv.cap) {
+    AcEvent *e = tv.ev + cell * tv.cap + len;
+    e->type = type;
+    e->q = q;
+    e->val = val;
+  }
+  ++len;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT, 2) void k_bdf(DNet n, const double *__restrict__ la_over,
+                                            int64_t n_cells, double *__restrict__ y,
+                                            const double *__restrict__ T, BdfParams P,
+                                            CellOut out, TapeView tv, WsView W,
+                                            unsigned *queue) {
+  extern __shared__ double sm[];
+  const int ns = n.ns, nr = n.nr;
+  double *f = sm, *yn = f + ns, *dd = yn + ns, *psi = dd + ns, *scl = psi + ns, *yp = scl + ns,
+         *dy = yp + ns, *rs = dy + ns;
+  double *part = rs + nr;
+  double *blk = part + (n.rhs.n_slot > 0 ? n.rhs.n_slot : 1);
+  double *red = blk + SB * SB;
+  int *redi = reinterpret_cast<int *>(red + 8 + 3 * (QMAX + 1) * (QMAX + 1));
+  __shared__ int64_t s_cell;
+
+  const size_t slot = blockIdx.x;
+  CellCtx cx;
+  cx.n = &n;
+  cx.kg = W.k + slot * W.k_stride;
+  cx.Jg = W.J + slot * W.j_stride;
+  cx.tailp = W.tail + slot * W.tail_stride;
+  cx.M = W.M + slot * W.m_stride;
+  cx.piv = W.piv + slot * W.piv_stride;
+  cx.D = W.D + slot * W.d_stride;
+  cx.lda = W.lda;
+  cx.rs = rs;
+  cx.part = part;
+  cx.blk = blk;
+  cx.red = red;
+  cx.redi = redi;
+  const double rtol = P.rtol, atol = P.atol, t_end = P.t_end;
+  const double tol = fmax(10.0 * 2.220446049250313e-16 / rtol, fmin(0.03, sqrt(rtol)));
+
+  for (int64_t iter = 0;; ++iter) {
+    if (threadIdx.x == 0)
+      s_cell = queue ? int64_t(atomicAdd(queue, 1u)) : int64_t(blockIdx.x) + iter * gridDim.x;
+    __syncthreads();
+    const int64_t cell = s_cell;
+    __syncthreads();
+    if (cell >= n_cells) break;
+
+    for (int i = 0; i < ST_N; ++i) cx.cnt[i] = 0;
+    int tlen = 0;
+    double *ycell = y + cell * ns;
+    const double Tc = T[cell];
+    bool bad = false;
+    for (int i = threadIdx.x; i < ns; i += NT) {
+      const double v = ycell[i];
+      if (!(isfinite(v) && v >= 0.0)) bad = true;
+    }
+    bad = wg_any<NT>(bad, red) || !(isfinite(Tc) && Tc > 0.0);
+    int status = AC_CELL_OK, q = 1, steps = 0;
+    const bool run = !bad && t_end > 0.0;
+    if (bad) status = AC_CELL_BADINPUT;
+    if (run) {
+      double L, invT;
+      cell_temperature(Tc, L, invT);
+      for_reactions<NT>(n, la_over, L, invT, [&](int j, double kj, uint32_t) { cx.kg[j] = kj; });
+      for (int x = threadIdx.x; x < ns; x += NT) {
+        const double v = ycell[x];
+        yn[x] = v;
+        cx.D[x] = v;
+        for (int m = 1; m < NDROW; ++m) cx.D[size_t(m) * ns + x] = 0.0;
+      }
+      __syncthreads();
+      cell_rhs<NT>(cx, yn, f);
+      // first step (Hairer, Norsett & Wanner, Sec. II.4, order 1)
+      double h;
+      if (P.h0 > 0.0) {
+        h = fmin(P.h0, t_end);
+      } else {
+        for (int x = threadIdx.x; x < ns; x += NT) scl[x] = atol + rtol * fabs(yn[x]);
+        __syncthreads();
+        const double d0 = wg_rms<NT>(yn, 1.0, scl, ns, red);
+        const double d1 = wg_rms<NT>(f, 1.0, scl, ns, red);
+        double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+        if (h0 > t_end) h0 = t_end;
+        for (int x = threadIdx.x; x < ns; x += NT) yp[x] = yn[x] + h0 * f[x];
+        __syncthreads();
+        cell_rhs<NT>(cx, yp, dy);
+        for (int x = threadIdx.x; x < ns; x += NT) dy[x] -= f[x];
+        __syncthreads();
+        const double d2 = wg_rms<NT>(dy, 1.0, scl, ns, red) / h0;
+        const double h1 = (d1 <= 1e-15 && d2 <= 1e-15) ? fmax(1e-6, h0 * 1e-3)
+                                                         : pow(0.01 / fmax(d1, d2), 1.0 / 2.0);
+        h = fmin(fmin(100.0 * h0, h1), t_end);
+      }
+      tape_put(tv, cell, tlen, EV_INIT, 1, h);
+      for (int x = threadIdx.x; x < ns; x += NT) cx.D[size_t(ns) + x] = h * f[x];
+      __syncthreads();
+      cell_jac<NT>(cx, yn);
+
+      int n_equal = 0;
+      bool lu_valid = false;
+      double t = 0.0, h_abs = h;
+      while (t < t_end) {
+        if (steps >= P.max_steps) {
+          status = AC_CELL_MAXSTEPS;
+          break;
+        }
+        const double hmin = 10.0 * (nextafter(t, INFINITY) - t);
+        bool jac_fresh = false;
+        int n_iter = 0;
+        double t_new = t, en = 0.0, safety = 0.0;
+        bool failed = false;
+        for (;;) {   // attempts
+          if (h_abs < hmin) {
+            status = AC_CELL_HMIN;
+            failed = true;
+            break;
+          }
+          t_new = t + h_abs;
+          if (t_new > t_end) {
+            t_new = t_end;
+            const double factor = (t_new - t) / h_abs;
+            rescale_diffs<NT>(cx, q, factor, ns);
+            tape_put(tv, cell, tlen, EV_RESCALE, q, factor);
+            n_equal = 0;
+            lu_valid = false;
+          }
+          h = t_new - t;
+          h_abs = h;
+          double gam_m[QMAX + 1];
+#pragma unroll
+          for (int m = 0; m <= QMAX; ++m) gam_m[m] = bdf_gamma(m);
+          const double alph_q = bdf_gamma(q);
+          for (int x = threadIdx.x; x < ns; x += NT) {
+            double s = 0.0;
+            for (int m = 0; m <= q; ++m) s += cx.D[size_t(m) * ns + x];
+            yp[x] = s;
+            scl[x] = atol + rtol * fabs(s);
+            double p = 0.0;
+            for (int m = 1; m <= q; ++m) p += gam_m[m] * cx.D[size_t(m) * ns + x];
+            psi[x] = p / alph_q;
+          }
+          __syncthreads();
+          const double c = h / alph_q;
+          bool conv = false;
+          for (;;) {
+            if (!lu_valid) {
+              cell_factor<NT>(cx, c);
+              lu_valid = true;
+            }
+            // simplified Newton
+            for (int x = threadIdx.x; x < ns; x += NT) {
+              yn[x] = yp[x];
+              dd[x] = 0.0;
+            }
+            __syncthreads();
+            double prev = 0.0;
+            int it;
+            for (it = 0; it < NEWTON_MAXITER; ++it) {
+              cell_rhs<NT>(cx, yn, f);
+              bool nonfinite = false;
+              for (int x = threadIdx.x; x < ns; x += NT)
+                if (!isfinite(f[x])) nonfinite = true;
+              if (wg_any<NT>(nonfinite, red)) break;
+              for (int x = threadIdx.x; x < ns; x += NT) dy[x] = c * f[x] - psi[x] - dd[x];
+              __syncthreads();
+              wg_solve<NT>(cx.M, cx.lda, ns, cx.piv, dy, false, blk);
+              const double dn = wg_rms<NT>(dy, 1.0, scl, ns, red);
+              double rate = 0.0;
+              if (it > 0) {
+                rate = dn / prev;
+                if (rate >= 1.0 || pow(rate, double(NEWTON_MAXITER - it)) / (1.0 - rate) * dn > tol)
+                  break;
+              }
+              for (int x = threadIdx.x; x < ns; x += NT) {
+                yn[x] += dy[x];
+                dd[x] += dy[x];
+              }
+              __syncthreads();
+              if (dn == 0.0 || (it > 0 && rate / (1.0 - rate) * dn < tol)) {
+                conv = true;
+                break;
+              }
+              prev = dn;
+            }
+            n_iter = it + 1;
+            cx.cnt[ST_NEWTON] += it < NEWTON_MAXITER ? it + 1 : NEWTON_MAXITER;
+            if (conv || jac_fresh) break;
+            cell_jac<NT>(cx, yp);
+            jac_fresh = true;
+            lu_valid = false;
+          }
+          if (!conv) {
+            h_abs *= 0.5;
+            rescale_diffs<NT>(cx, q, 0.5, ns);
+            tape_put(tv, cell, tlen, EV_RESCALE, q, 0.5);
+            n_equal = 0;
+            lu_valid = false;
+            cx.cnt[ST_REJ_NEWTON]++;
+            continue;
+          }
+          safety = 0.9 * (2 * NEWTON_MAXITER + 1) / (2 * NEWTON_MAXITER + n_iter);
+          for (int x = threadIdx.x; x < ns; x += NT) scl[x] = atol + rtol * fabs(yn[x]);
+          __syncthreads();
+          en = wg_rms<NT>(dd, bdf_errc(q), scl, ns, red);
+          if (en > 1.0) {
+            const double factor = fmax(MIN_FACTOR, safety * pow_neg(en, 1.0 / (q + 1)));
+            h_abs *= factor;
+            rescale_diffs<NT>(cx, q, factor, ns);
+            tape_put(tv, cell, tlen, EV_RESCALE, q, factor);
+            n_equal = 0;
+            lu_valid = false;
+            cx.cnt[ST_REJ_ERR]++;
+            continue;
+          }
+          break;
+        }
+        if (failed) break;
+        // accepted
+        t = t_new;
+        ++steps;
+        tape_put(tv, cell, tlen, EV_STEP, q, h);
+        for (int x = threadIdx.x; x < ns; x += NT) {
+          double *Dx = cx.D + x;
+          Dx[size_t(q + 2) * ns] = dd[x] - Dx[size_t(q + 1) * ns];
+          Dx[size_t(q + 1) * ns] = dd[x];
+          for (int i = q; i >= 0; --i) Dx[size_t(i) * ns] += Dx[size_t(i + 1) * ns];
+        }
+        __syncthreads();
+        ++n_equal;
+        if (n_equal < q + 1) continue;
+        const double em = q > 1 ? wg_rms<NT>(cx.D + size_t(q) * ns, bdf_errc(q - 1), scl, ns, red) : INFINITY;
+        const double ep = q < P.q_max ? wg_rms<NT>(cx.D + size_t(q + 2) * ns, bdf_errc(q + 1), scl, ns, red) : INFINITY;
+        const double fac[3] = {pow_neg(em, 1.0 / q), pow_neg(en, 1.0 / (q + 1)),
+                               pow_neg(ep, 1.0 / (q + 2))};
+        int best = 0;
+        for (int i = 1; i < 3; ++i)
+          if (fac[i] > fac[best]) best = i;
+        q += best - 1;
+        const double factor = fmin(MAX_FACTOR, safety * fac[best]);
+        h_abs *= factor;
+        rescale_diffs<NT>(cx, q, factor, ns);
+        tape_put(tv, cell, tlen, EV_RESCALE, q, factor);
+        n_equal = 0;
+        lu_valid = false;
+      }
+      for (int x = threadIdx.x; x < ns; x += NT) ycell[x] = cx.D[x];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      if (out.status) out.status[cell] = status;
+      if (out.stats) {
+        int *st = out.stats + cell * ST_N;
+        for (int i = 0; i < ST_N; ++i) st[i] = cx.cnt[i];
+        st[ST_STEPS] = steps;
+        st[ST_QLAST] = run ? q : 0;
+      }
+      if (tv.len) tv.len[cell] = tlen > tv.cap ? -1 : tlen;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_reset_queue(unsigned *q) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0u;
+}
+
+// ------------------------------------------------------- standalone LU
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_lu_factor(int n, int lda, int64_t nmat, double *A,
+                                                  int *piv, int *info) {
+  __shared__ double red[NT / 64];
+  __shared__ int redi[NT / 64];
+  for (int64_t m = blockIdx.x; m < nmat; m += gridDim.x) {
+    const int inf = wg_lu<NT>(A + size_t(m) * n * lda, lda, n, piv + size_t(m) * n, red, redi);
+    if (threadIdx.x == 0 && info) info[m] = inf;
+    __syncthreads();
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_lu_solve(int n, int lda, int64_t nmat, const double *LU,
+                                                 const int *piv, double *b, int trans) {
+  extern __shared__ double sm[];
+  double *x = sm, *blk = sm + n;
+  for (int64_t m = blockIdx.x; m < nmat; m += gridDim.x) {
+    double *bm = b + size_t(m) * n;
+    for (int i = threadIdx.x; i < n; i += NT) x[i] = bm[i];
+    __syncthreads();
+    wg_solve<NT>(LU + size_t(m) * n * lda, lda, n, piv + size_t(m) * n, x, trans != 0, blk);
+    for (int i = threadIdx.x; i < n; i += NT) bm[i] = x[i];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- launch
+
+size_t bdf_lds_bytes(const DNet &n) {
+  return sizeof(double) * (size_t(7) * n.ns + n.nr + (n.rhs.n_slot > 0 ? n.rhs.n_slot : 1) +
+                           SB * SB + 8 + 3 * (QMAX + 1) * (QMAX + 1)) +
+         sizeof(int) * 8;
+}
+
+int bdf_resident_blocks(const DNet &n) {
+  const size_t lds = bdf_lds_bytes(n);
+  if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(k_bdf<BDF_NT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bdf<BDF_NT>, BDF_NT, lds) !=
+          hipSuccess || per_cu <= 0)
+    per_cu = 1;
+  int dev = 0, cus = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return per_cu * (cus > 0 ? cus : 256);
+}
+
+hipError_t launch_bdf(const DNet &n, const double *la, int64_t n_cells, double *y, const double *T,
+                      const BdfParams &P, const CellOut &out, const TapeView &tv, const WsView &W,
+                      unsigned *queue, int grid, hipStream_t st) {
+  if (n_cells == 0) return hipSuccess;
+  const size_t lds = bdf_lds_bytes(n);
+  if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(k_bdf<BDF_NT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (queue) hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, queue);
+  const int g = int(n_cells < grid ? n_cells : grid);
+  hipLaunchKernelGGL(k_bdf<BDF_NT>, dim3(g), dim3(BDF_NT), lds, st, n, la, n_cells, y, T, P, out,
+                     tv, W, queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_lu_factor(int n, int lda, int64_t nmat, double *A, int *piv, int *info,
+                            hipStream_t st) {
+  if (nmat == 0) return hipSuccess;
+  const int g = int(nmat < 4096 ? nmat : 4096);
+  hipLaunchKernelGGL(k_lu_factor<BDF_NT>, dim3(g), dim3(BDF_NT), 0, st, n, lda, nmat, A, piv, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_lu_solve(int n, int lda, int64_t nmat, const double *LU, const int *piv,
+                           double *b, int trans, hipStream_t st) {
+  if (nmat == 0) return hipSuccess;
+  const int g = int(nmat < 4096 ? nmat : 4096);
+  const size_t lds = sizeof(double) * (size_t(n) + SB * SB);
+  if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(k_lu_solve<BDF_NT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  hipLaunchKernelGGL(k_lu_solve<BDF_NT>, dim3(g), dim3(BDF_NT), lds, st, n, lda, nmat, LU, piv, b,
+                     trans);
+  return hipGetLastError();
+}
+
+}  // namespace ac

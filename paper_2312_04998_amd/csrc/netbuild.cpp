@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <numeric>
 #include <queue>
@@ -191,7 +192,8 @@ std::string build_network(int ns, int nr, const int32_t *reactants, const int32_
   if (ordering < 0 || ordering > 2) return "unknown ordering";
   if (chunk < 0 || sell_c < 0 || sell_sigma < 0) return "negative chunk/sell parameter";
   chunk = chunk ? chunk : 32;
-  sell_c = sell_c ? sell_c : 64;
+  if (sell_c != 0 && sell_c != 64) return "sell_c must be 64 (one wavefront per slice)";
+  sell_c = 64;
   sell_sigma = sell_sigma ? sell_sigma : (1 << 30);
   if (check_balance && (!composition || n_elem <= 0)) return "balance check needs a composition";
 
@@ -294,7 +296,7 @@ std::string build_network(int ns, int nr, const int32_t *reactants, const int32_
   }
   H.j_row_ptr.assign(1, 0);
   std::vector<std::vector<uint32_t>> jseg;
-  std::vector<int32_t> entry_row;
+  std::vector<int32_t> &entry_row = H.jent_row;
   for (int i = 0; i < ns; ++i) {
     for (auto &kv : jrow[i]) {
       H.j_col.push_back(kv.first);
@@ -308,8 +310,57 @@ std::string build_network(int ns, int nr, const int32_t *reactants, const int32_
   jorder.reserve(H.j_col.size());
   for (int k = 0; k < ns; ++k)
     for (int e = H.j_row_ptr[H.perm[k]]; e < H.j_row_ptr[H.perm[k] + 1]; ++e) jorder.push_back(e);
-  build_schedule(jseg, jorder, chunk, sell_c, sell_sigma, H.jac);
-  build_schedule(gyseg, H.perm, chunk, sell_c, sell_sigma, H.gy);
+  // Jacobian and VJP term lists keep their natural chunk order in SELL
+  // (sigma = 1), so consecutive lanes write consecutive outputs
+  build_schedule(jseg, jorder, chunk, sell_c, 1, H.jac);
+  {
+    const size_t ne = jseg.size();
+    const uint32_t pad = pack_item(0, -1, 0);
+    H.jhead0.assign(ne, pad);
+    H.jhead1.assign(ne, pad);
+    H.jtaildesc.assign(ne, 0u);
+    std::vector<std::vector<uint32_t>> tails(ne);
+    std::vector<int32_t> tail_order;
+    for (size_t e = 0; e < ne; ++e) {
+      const auto &t = jseg[e];
+      if (t.size() > 0) H.jhead0[e] = t[0];
+      if (t.size() > 1) H.jhead1[e] = t[1];
+      if (t.size() > 2) {
+        tails[e].assign(t.begin() + 2, t.end());
+        tail_order.push_back(int32_t(e));
+      }
+    }
+    // every tail chunk writes a slot: force "split" handling by building the
+    // schedule over the tails and remapping single-chunk tails to slots too
+    build_schedule(tails, tail_order, chunk, sell_c, 1, H.jtail);
+    int slot = 0;
+    for (int c = 0, k = 0; k < H.jtail.n_seg; ++k) {
+      const int e = H.jtail.seg_out[k];
+      const int c0 = H.jtail.seg_chunk[k], c1 = H.jtail.seg_chunk[k + 1];
+      if (c1 - c0 > 255) return "Jacobian entry with too many terms";
+      H.jtaildesc[e] = (uint32_t(slot) << 8) | uint32_t(c1 - c0);
+      for (c = c0; c < c1; ++c) H.jtail.chunk_dst[c] = -1 - slot++;
+    }
+    H.jtail.n_slot = slot;
+    H.jtail.n_multi = 0;
+    H.jtail.multi_out.clear();
+    H.jtail.multi_slot.assign(1, 0);
+  }
+  build_schedule(gyseg, H.perm, chunk, sell_c, 1, H.gy);
+  // packed per-reaction record (see HostNet::rxpack)
+  H.rxpack.assign(size_t(nr) * 16, 0u);
+  for (int j = 0; j < nr; ++j) {
+    uint32_t *r = &H.rxpack[size_t(j) * 16];
+    double par[3] = {H.log_alpha[j], H.beta[j], H.gamma[j]};
+    std::memcpy(r, par, sizeof(par));
+    r[6] = H.rpair[j];
+    uint16_t half[8];
+    for (int q = 0; q < 8; ++q) half[q] = 0xFFFF;
+    int q = 0;
+    for (int p = H.s_col_ptr[j]; p < H.s_col_ptr[j + 1]; ++p)
+      half[q++] = uint16_t(H.s_row[p] | ((H.s_cval[p] & 31) << 11));
+    std::memcpy(r + 8, half, sizeof(half));
+  }
   *code = AC_OK;
   return "";
 }

@@ -48,6 +48,9 @@ struct HostNet {
   // reaction data
   std::vector<double> log_alpha, beta, gamma;
   std::vector<uint32_t> rpair;        // reactant a | b << 16, 0xFFFF = none
+  // per reaction: ln alpha, beta, gamma, rpair, and the net column of S as up
+  // to 8 16-bit (species | coef << 11) halves (0xFFFF = none), 64 bytes
+  std::vector<uint32_t> rxpack;
   // S in CSR (natural rows, reactions ascending) and CCS (per reaction)
   std::vector<int32_t> s_row_ptr, s_col, s_val;
   std::vector<int32_t> s_col_ptr, s_row, s_cval;
@@ -56,6 +59,13 @@ struct HostNet {
   std::vector<int32_t> perm;          // species traversal order
   Schedule rhs;                       // rows of S: items (j, NONE, S_ij)
   Schedule jac;                       // pattern entries: items (j, other reactant, S_ij*mult)
+  // Two-tier Jacobian: per entry e (natural order) its first two terms
+  // (PAD if absent) and a tail descriptor (first slot << 8 | number of
+  // slots, 0 = no tail); the remaining terms of every entry form the
+  // `jtail` schedule whose chunk partials land in those slots.
+  std::vector<uint32_t> jhead0, jhead1, jtaildesc;
+  std::vector<int32_t> jent_row;      // row of every pattern entry (columns: j_col)
+  Schedule jtail;
   Schedule gy;                        // species a: items (j, other reactant, mult) over slots of a
   int layout = 0, ordering = 0;
 };
