@@ -35,6 +35,7 @@ def parse():
     p.add_argument("--cells", type=int, default=65536)
     p.add_argument("--layout", default="sell")
     p.add_argument("--ordering", default="nnz")
+    p.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
     p.add_argument("--no-table", action="store_true", help="skip the layout x ordering table")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -104,7 +105,7 @@ def main():
     dev = torch.device("cuda:0")
     y = torch.from_numpy(cells.y0).to(dev)
     T = torch.from_numpy(cells.T).to(dev)
-    N = acm.Network.from_synth(net, layout=args.layout, ordering=args.ordering)
+    N = acm.Network.from_synth(net, layout=args.layout, ordering=args.ordering, block=args.block)
     dydt = torch.empty_like(y)
     jv = torch.empty((args.cells, N.nnz_j), dtype=torch.float64, device=dev)
     k = torch.empty((args.cells, nr), dtype=torch.float64, device=dev)
@@ -158,7 +159,22 @@ def main():
                       "hbm_frac": bytes_of[name] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     table = {}
+    blocks = {}
     if not args.no_table:
+        for blk in (256, 512, 1024):
+            M = acm.Network.from_synth(net, layout=args.layout, ordering=args.ordering, block=blk)
+            for _ in range(2):
+                acm.ac_rhs(M, None, y, T, dydt)
+                acm.ac_jac(M, None, y, T, jv)
+            torch.cuda.synchronize()
+            tt = Timer(torch)
+            for _ in range(5):
+                tt.run("rhs", lambda: acm.ac_rhs(M, None, y, T, dydt))
+                tt.run("jac", lambda: acm.ac_jac(M, None, y, T, jv))
+                tt.run("vjp", lambda: acm.ac_vjp(M, None, y, T, v, gy, gl))
+            torch.cuda.synchronize()
+            blocks[str(blk)] = {kk: round(tt.mean_ms(kk), 4) for kk in ("rhs", "jac", "vjp")}
+            M.close()
         for lay in ("csr", "sell", "coo"):
             for order in ("natural", "nnz", "rcm"):
                 M = acm.Network.from_synth(net, layout=lay, ordering=order)
@@ -201,6 +217,7 @@ def main():
                      "bytes_per_launch": bytes_of["jac"], "avg_ms": jac_ms},
         "kernels": kern,
         "rhs_layout_table": table,
+        "block_table_ms": blocks,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(net, cells, args.cpu_seconds)

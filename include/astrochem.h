@@ -186,7 +186,10 @@ ac_status ac_vjp(const ac_net *net, const double *log_alpha, int64_t n_cells, co
  * species), one per cell. A: [n_mat][n][lda] row-major DEVICE array,
  * factored in place as P A = L U with unit lower L (partial pivoting, whole
  * rows swapped, piv[k] = row exchanged with row k at step k); info[m] = 0 or
- * 1 + index of the first exactly-zero pivot (info may be NULL). lda >= n. */
+ * 1 + index of the first exactly-zero pivot (info may be NULL). lda >= n;
+ * n <= 1024 (AC_ELIMIT otherwise: a panel column lives in one workgroup's
+ * registers, two rows per thread). Errors: AC_EINVAL for bad sizes or NULL
+ * arrays with n_mat > 0, AC_EHIP for a failed launch. */
 ac_status ac_lu_factor(int32_t n, int32_t lda, int64_t n_mat, double *A, int32_t *piv,
                        int32_t *info, ac_stream stream);
 /* Solves A x = b (trans = 0) or A^T x = b (trans = 1) in place in b

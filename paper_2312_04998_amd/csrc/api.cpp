@@ -11,6 +11,7 @@
 
 #include "../../include/astrochem.h"
 #include "devbdf.h"
+#include "devla.h"
 #include "devnet.h"
 #include "netbuild.h"
 
@@ -389,6 +390,8 @@ ac_status ac_lu_factor(int32_t n, int32_t lda, int64_t n_mat, double *A, int32_t
                        int32_t *info, ac_stream stream) {
   if (n <= 0 || lda < n || n_mat < 0) return fail(AC_EINVAL, "need n > 0, lda >= n, n_mat >= 0");
   if (n_mat && (!A || !piv)) return fail(AC_EINVAL, "null A or piv");
+  if (n > 2 * ac::BDF_NT || sizeof(double) * (size_t(n) * 16 + 256) > 160 * 1024)
+    return fail(AC_ELIMIT, "n too large for a workgroup-resident LU panel (n <= 1024)");
   hipError_t e = ac::launch_lu_factor(n, lda, n_mat, A, piv, info, hipStream_t(stream));
   return e == hipSuccess ? AC_OK : hip_fail(e, "ac_lu_factor launch");
 }
@@ -397,7 +400,7 @@ ac_status ac_lu_solve(int32_t n, int32_t lda, int64_t n_mat, const double *LU,
                       const int32_t *piv, double *b, int32_t trans, ac_stream stream) {
   if (n <= 0 || lda < n || n_mat < 0) return fail(AC_EINVAL, "need n > 0, lda >= n, n_mat >= 0");
   if (n_mat && (!LU || !piv || !b)) return fail(AC_EINVAL, "null LU, piv or b");
-  if (sizeof(double) * (size_t(n) + 32 * 32) > 160 * 1024)
+  if (sizeof(double) * (size_t(2) * n + ac::SB * ac::SBP) + sizeof(int) * size_t(n) > 160 * 1024)
     return fail(AC_ELIMIT, "n too large for an LDS-resident right-hand side");
   hipError_t e = ac::launch_lu_solve(n, lda, n_mat, LU, piv, b, trans, hipStream_t(stream));
   return e == hipSuccess ? AC_OK : hip_fail(e, "ac_lu_solve launch");
@@ -423,7 +426,7 @@ ac_status ac_ws_create(const ac_net *net, int32_t n_slots, ac_ws **out) {
   *out = nullptr;
   if (!net->dbuf) return fail(AC_EHIP, "network has no device copy (no GPU at creation)");
   if (n_slots < 0) return fail(AC_EINVAL, "n_slots < 0");
-  if (ac::bdf_lds_bytes(net->d) > 160 * 1024)
+  if (net->d.ns > 2 * ac::BDF_NT || ac::bdf_lds_bytes(net->d) > 160 * 1024)
     return fail(AC_ELIMIT, "network too large for the integrator's LDS working set");
   const int resident = ac::bdf_resident_blocks(net->d);
   ac_ws *ws = new (std::nothrow) ac_ws();
@@ -438,7 +441,7 @@ ac_status ac_ws_create(const ac_net *net, int32_t n_slots, ac_ws **out) {
   const size_t t_b = r256(sizeof(double) * size_t(std::max(1, net->host.jtail.n_slot)));
   const size_t d_b = r256(sizeof(double) * size_t(8) * ns);
   const size_t k_b = r256(sizeof(double) * size_t(nr));
-  const size_t p_b = r256(sizeof(int) * size_t(ns));
+  const size_t p_b = r256(sizeof(int) * size_t(2 * ns));
   const size_t per = m_b + j_b + t_b + d_b + k_b + p_b;
   ws->bytes = per * size_t(ws->n_slots) + 256;
   hipError_t e = hipMalloc(&ws->buf, ws->bytes);

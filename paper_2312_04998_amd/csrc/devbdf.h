@@ -10,7 +10,7 @@
 
 namespace ac {
 
-constexpr int BDF_NT = 256;   // threads per integrator workgroup (4 wavefronts)
+constexpr int BDF_NT = 512;   // threads per integrator workgroup (8 wavefronts)
 
 // per-cell counters, same order as the public ac_stat enum
 enum { ST_STEPS = 0, ST_REJ_ERR, ST_REJ_NEWTON, ST_NEWTON, ST_JAC, ST_LU, ST_RHS, ST_QLAST, ST_N };
@@ -40,7 +40,7 @@ struct TapeView {
 // Global workspace slots (one per resident workgroup).
 struct WsView {
   double *M, *J, *tail, *D, *k;
-  int *piv;
+  int *piv;         // per slot: pivots [ns] then the row permutation [ns]
   size_t m_stride, j_stride, tail_stride, d_stride, k_stride, piv_stride;
   int lda;
 };

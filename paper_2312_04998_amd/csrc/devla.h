@@ -1,9 +1,11 @@
 // Workgroup-level dense FP64 linear algebra for the Newton step of the
 // implicit integrator: LU with partial pivoting (right-looking, 16-column
-// panels, trailing update on the FP64 matrix cores) and the triangular
-// solves A x = b and A^T x = b. One workgroup owns one matrix; matrices are
-// row-major with leading dimension lda in global memory (L2-resident per
-// slot), right-hand sides live in LDS.
+// panels factored in LDS, row swaps outside the panel applied afterwards,
+// trailing update on the FP64 matrix cores) and the triangular solves
+// A x = b and A^T x = b. One workgroup owns one matrix; matrices are
+// row-major with leading dimension lda in global memory, right-hand sides
+// live in LDS. Every loop over matrix data keeps many independent loads in
+// flight: a single workgroup per cell is latency-bound otherwise.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,6 +16,17 @@
 namespace ac {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+
+constexpr int PW = 16;   // LU panel width
+constexpr int SB = 64;        // triangular-solve block
+constexpr int SBP = SB + 1;   // its LDS row stride (odd: row-wise lane reads avoid bank conflicts)
+
+// LDS the factorisation / solves need besides the right-hand side (doubles).
+__host__ __device__ inline int la_scratch_doubles(int n) {
+  const int pan = n * PW + PW * PW;
+  const int blk = SB * SBP;
+  return pan > blk ? pan : blk;
+}
 
 // Sum over the workgroup; every thread gets the same value (fixed tree).
 template <int NT>
@@ -29,256 +42,562 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
   return s;
 }
 
-// Largest |value|, smallest index among ties; every thread gets the pair.
+// A22 -= L21 U12 for the panel at k0 of width kw (A22 starts at kend =
+// k0 + kw). L21 is read from the LDS panel (row kw + r of `pan` is matrix
+// row kend + r), U12 and A22 from global memory. Each wave owns 32x32
+// blocks (2x2 tiles of 16x16); each tile is four v_mfma_f64_16x16x4
+// products (K = 16). Operand lanes: A[l%16][l/16], B[l/16][l%16]; result
+// element v of lane l is row l/16 + 4v, column l%16.
 template <int NT>
-__device__ __forceinline__ void wg_argmax(double &v, int &idx, double *red, int *redi) {
+__device__ __forceinline__ void trailing_block(double *__restrict__ A, int lda, int n, int k0,
+                                               int kw, const double *pan, int nb, int t,
+                                               d4_t (&acc)[2][2], double (&bop)[2][4], bool load) {
+  const int kend = k0 + kw;
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int bi = t / nb, bj = t - bi * nb;
+  const int r0 = kend + 32 * bi, c0 = kend + 32 * bj;
+  if (load) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(v, o);
-    const int oi = __shfl_xor(idx, o);
-    if (ov > v || (ov == v && oi < idx)) {
-      v = ov;
-      idx = oi;
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int col = c0 + 16 * b + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = r0 + 16 * a + lk + 4 * v;
+          acc[a][b][v] = (row < n && col < n) ? A[size_t(row) * lda + col] : 0.0;
+        }
+      }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = c0 + 16 * b + li;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int kc = 4 * kk + lk;
+        bop[b][kk] = (kc < kw && col < n) ? A[size_t(k0 + kc) * lda + col] : 0.0;
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int pr = kw + 32 * bi + 16 * a + li;   // panel row of L21
+    const bool ok = kend + 32 * bi + 16 * a + li < n;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const double aop = ok ? -pan[pr * PW + 4 * kk + lk] : 0.0;
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[b][kk], acc[a][b], 0, 0, 0);
     }
   }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = c0 + 16 * b + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 16 * a + lk + 4 * v;
+        if (row < n && col < n) A[size_t(row) * lda + col] = acc[a][b][v];
+      }
+    }
+}
+
+// A22 -= L21 U12 for the panel at k0 of width kw (A22 starts at kend =
+// k0 + kw). L21 is read from the LDS panel (row kw + r of `pan` is matrix
+// row kend + r), U12 and A22 from global memory. Each wave owns 32x32
+// blocks (2x2 tiles of 16x16, each four v_mfma_f64_16x16x4 products with
+// K = 16) and keeps two blocks' loads in flight. Operand lanes:
+// A[l%16][l/16], B[l/16][l%16]; result element v of lane l is row
+// l/16 + 4v, column l%16.
+template <int NT>
+__device__ __forceinline__ void trailing_update(double *__restrict__ A, int lda, int n, int k0,
+                                                int kw, const double *pan) {
+  const int m = n - (k0 + kw);
+  if (m <= 0) return;
+  const int nb = (m + 31) >> 5, nblk = nb * nb;
+  constexpr int NW = NT / 64;
+  for (int t = threadIdx.x >> 6; t < nblk; t += 2 * NW) {
+    d4_t acc0[2][2], acc1[2][2];
+    double b0[2][4], b1[2][4];
+    const bool two = t + NW < nblk;
+    trailing_block<NT>(A, lda, n, k0, kw, pan, nb, t, acc0, b0, true);
+    if (two) trailing_block<NT>(A, lda, n, k0, kw, pan, nb, t + NW, acc1, b1, true);
+    trailing_block<NT>(A, lda, n, k0, kw, pan, nb, t, acc0, b0, false);
+    if (two) trailing_block<NT>(A, lda, n, k0, kw, pan, nb, t + NW, acc1, b1, false);
+  }
+}
+
+// Value of lane `src` (wave-uniform) of a double, through scalar registers.
+__device__ __forceinline__ double bcast(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// Lane exchange through the DPP crossbar (no LDS round trip); CTRL is a
+// full-wave data-parallel-primitive control code.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double &v, int &idx) {
+  const double ov = dpp_d<CTRL>(v);
+  const int oi = __builtin_amdgcn_update_dpp(0, idx, CTRL, 0xF, 0xF, false);
+  if (ov > v || (ov == v && oi < idx)) {
+    v = ov;
+    idx = oi;
+  }
+}
+
+__device__ __forceinline__ void argmax_pick(double &v, int &idx, double ov, int oi) {
+  if (ov > v || (ov == v && oi < idx)) {
+    v = ov;
+    idx = oi;
+  }
+}
+
+// Pivot search over the workgroup: largest value, smallest index among
+// ties; every thread gets the pair. Within a wave: quad swaps, then the
+// half-row and row mirrors leave every 16-lane row with its row's best,
+// and the four rows are combined through scalar registers. Leaves red/redi
+// to be reused only after the caller's next barrier.
+template <int NT>
+__device__ __forceinline__ void wg_argmax_open(double &v, int &idx, double *red, int *redi) {
+  argmax_step<0xB1>(v, idx);    // quad_perm [1,0,3,2]
+  argmax_step<0x4E>(v, idx);    // quad_perm [2,3,0,1]
+  argmax_step<0x141>(v, idx);   // row_half_mirror
+  argmax_step<0x140>(v, idx);   // row_mirror
+  double w = bcast(v, 0);
+  int wi = __builtin_amdgcn_readlane(idx, 0);
+  argmax_pick(w, wi, bcast(v, 16), __builtin_amdgcn_readlane(idx, 16));
+  argmax_pick(w, wi, bcast(v, 32), __builtin_amdgcn_readlane(idx, 32));
+  argmax_pick(w, wi, bcast(v, 48), __builtin_amdgcn_readlane(idx, 48));
   if ((threadIdx.x & 63) == 0) {
-    red[threadIdx.x >> 6] = v;
-    redi[threadIdx.x >> 6] = idx;
+    red[threadIdx.x >> 6] = w;
+    redi[threadIdx.x >> 6] = wi;
   }
   __syncthreads();
   v = red[0];
   idx = redi[0];
 #pragma unroll
-  for (int w = 1; w < NT / 64; ++w)
-    if (red[w] > v || (red[w] == v && redi[w] < idx)) {
-      v = red[w];
-      idx = redi[w];
-    }
-  __syncthreads();
+  for (int w2 = 1; w2 < NT / 64; ++w2) argmax_pick(v, idx, red[w2], redi[w2]);
 }
 
-// A22 -= L21 U12 for the panel [k0, kend): 16x16 output tiles per wave,
-// each the sum of ceil((kend-k0)/4) v_mfma_f64_16x16x4 products. Operand
-// lanes: A[l%16][l/16], B[l/16][l%16]; result element v of lane l is row
-// l/16 + 4v, column l%16.
-template <int NT>
-__device__ __forceinline__ void trailing_update(double *__restrict__ A, int lda, int n, int k0,
-                                                int kend) {
-  const int m = n - kend;
-  if (m <= 0) return;
-  const int nt = (m + 15) >> 4;
-  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  for (int t = threadIdx.x >> 6; t < nt * nt; t += NT / 64) {
-    const int ti = t / nt, tj = t - ti * nt;
-    const int r0 = kend + 16 * ti, c0 = kend + 16 * tj;
-    const int col = c0 + li;
-    d4_t acc;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = r0 + lk + 4 * v;
-      acc[v] = (row < n && col < n) ? A[size_t(row) * lda + col] : 0.0;
-    }
-    const int ar = r0 + li;
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int kc = k0 + 4 * kk + lk;
-      const double a = (ar < n && kc < kend) ? A[size_t(ar) * lda + kc] : 0.0;
-      const double b = (kc < kend && col < n) ? A[size_t(kc) * lda + col] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, b, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = r0 + lk + 4 * v;
-      if (row < n && col < n) A[size_t(row) * lda + col] = acc[v];
-    }
-  }
-}
-
-// In-place P A = L U (unit lower L), piv[k] = row swapped with row k at
-// step k (whole rows swapped). Returns 0 or 1 + the first zero pivot.
-// red: >= NT/64 doubles, redi: >= NT/64 ints of LDS.
-template <int NT>
-__device__ int wg_lu(double *__restrict__ A, int lda, int n, int *__restrict__ piv, double *red,
-                     int *redi) {
-  int info = 0;
-  for (int k0 = 0; k0 < n; k0 += 16) {
-    const int kend = k0 + 16 < n ? k0 + 16 : n;
-    for (int c = k0; c < kend; ++c) {
+// One column c of the panel factorisation (see panel_factor), unrolled
+// at compile time so that the register-resident rows are indexed by
+// constants only.
+template <int NT, int R, int C>
+struct PanelColumns {
+  static __device__ __forceinline__ void run(double (&a)[R][PW], int (&lp)[R], int k0, int kw, int m,
+                                             double *urow, double *red, int *redi, int *ipiv,
+                                             int &info) {
+    if (C < kw) {
       double best = -1.0;
-      int bi = INT_MAX;
-      for (int i = c + threadIdx.x; i < n; i += NT) {
-        const double v = fabs(A[size_t(i) * lda + c]);
-        if (v > best) {
-          best = v;
-          bi = i;
+      int bl = INT_MAX;
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (lp[i] < m && lp[i] >= C) {
+          const double v = fabs(a[i][C]);
+          if (v > best || (v == best && lp[i] < bl)) {
+            best = v;
+            bl = lp[i];
+          }
         }
-      }
-      wg_argmax<NT>(best, bi, red, redi);
-      const int p = best < 0.0 ? c : bi;
-      if (threadIdx.x == 0) piv[c] = p;
-      if (p != c)
-        for (int j = threadIdx.x; j < n; j += NT) {
-          const double t = A[size_t(c) * lda + j];
-          A[size_t(c) * lda + j] = A[size_t(p) * lda + j];
-          A[size_t(p) * lda + j] = t;
-        }
+      wg_argmax_open<NT>(best, bl, red, redi);
+      const int L = best < 0.0 ? C : bl;
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (lp[i] == L)
+#pragma unroll
+          for (int j = 0; j < PW; ++j) urow[j] = a[i][j];
+      if (threadIdx.x == 0) ipiv[C] = L;
       __syncthreads();
-      const double pivot = A[size_t(c) * lda + c];
+      const double pivot = urow[C];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        if (lp[i] == C)
+          lp[i] = L;
+        else if (lp[i] == L)
+          lp[i] = C;
+      }
       if (pivot != 0.0) {
-        const double *Ac = A + size_t(c) * lda;
-        for (int i = c + 1 + threadIdx.x; i < n; i += NT) {
-          double *Ai = A + size_t(i) * lda;
-          const double l = Ai[c] / pivot;
-          Ai[c] = l;
-          for (int j = c + 1; j < kend; ++j) Ai[j] -= l * Ac[j];
-        }
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+          if (lp[i] > C && lp[i] < m) {
+            const double l = a[i][C] / pivot;
+            a[i][C] = l;
+#pragma unroll
+            for (int j = C + 1; j < PW; ++j) a[i][j] -= l * urow[j];
+          }
       } else if (!info) {
-        info = c + 1;
+        info = k0 + C + 1;
       }
-      __syncthreads();
+      PanelColumns<NT, R, C + 1>::run(a, lp, k0, kw, m, urow, red, redi, ipiv, info);
     }
-    // U12 = L11^{-1} A12, one column per thread
-    for (int j = kend + threadIdx.x; j < n; j += NT)
-      for (int r = k0 + 1; r < kend; ++r) {
-        double s = A[size_t(r) * lda + j];
-        for (int q = k0; q < r; ++q) s -= A[size_t(r) * lda + q] * A[size_t(q) * lda + j];
-        A[size_t(r) * lda + j] = s;
+  }
+};
+
+template <int NT, int R>
+struct PanelColumns<NT, R, PW> {
+  static __device__ __forceinline__ void run(double (&)[R][PW], int (&)[R], int, int, int, double *,
+                                             double *, int *, int *, int &) {}
+};
+
+// Factors the m x kw panel at (k0, k0) with partial pivoting. Thread t
+// keeps panel rows t, t + NT, ... (R of them) in registers; row exchanges
+// are not carried out but tracked: lp[i] is the current (logical) position
+// of the thread's i-th row, so the pivot choice, the multipliers and the
+// final order are those of the explicit-swap algorithm. Two barriers per
+// column: one for the pivot search, one to publish the pivot row (urow, PW
+// doubles of LDS). On return the factored panel is in LDS (`pan`, logical
+// order) and in A, ipiv[c] is the logical row exchanged with row c, and
+// mv holds the (destination, source) row moves the other columns need.
+template <int NT, int R>
+__device__ __forceinline__ void panel_factor(double *__restrict__ A, int lda, int k0, int kw, int m,
+                                             double *pan, double *urow, double *red, int *redi,
+                                             int *ipiv, int *mv, int &info) {
+  double a[R][PW];
+  int lp[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int r = threadIdx.x + i * NT;
+    lp[i] = r;
+#pragma unroll
+    for (int j = 0; j < PW; ++j)
+      a[i][j] = (r < m && j < kw) ? A[size_t(k0 + r) * lda + k0 + j] : 0.0;
+  }
+  PanelColumns<NT, R, 0>::run(a, lp, k0, kw, m, urow, red, redi, ipiv, info);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int r = threadIdx.x + i * NT;
+    if (r < m) {
+#pragma unroll
+      for (int j = 0; j < PW; ++j) pan[lp[i] * PW + j] = a[i][j];
+#pragma unroll
+      for (int j = 0; j < PW; ++j)
+        if (j < kw) A[size_t(k0 + lp[i]) * lda + k0 + j] = a[i][j];
+      if (lp[i] != r) {
+        const int s = atomicAdd(mv, 1);
+        mv[2 + 2 * s] = lp[i];
+        mv[3 + 2 * s] = r;
       }
+    }
+  }
+}
+
+// In-place P A = L U (unit lower L). piv[k] = row exchanged with row k at
+// step k (LAPACK convention, whole rows); perm[i] = original row that ends
+// up in row i (so P b = b[perm]). Returns 0 or 1 + the first zero pivot.
+// n <= 2 * NT. pan: la_scratch_doubles(n) doubles of LDS; red/redi: NT/64
+// entries; ipiv: 9*PW + 2 ints of LDS.
+template <int NT>
+__device__ __forceinline__ int wg_lu(double *__restrict__ A, int lda, int n, int *__restrict__ piv,
+                                     int *__restrict__ perm, double *pan, double *red, int *redi,
+                                     int *ipiv) {
+  int info = 0;
+  int *mv = ipiv + PW;                       // [2 + 4 * PW] ints: count, pad, (dst, src) pairs
+  double *inv = pan + size_t(n) * PW;        // PW x PW: L11^{-1} (first PW doubles: pivot row)
+  for (int k0 = 0; k0 < n; k0 += PW) {
+    const int kw = k0 + PW < n ? PW : n - k0;
+    const int m = n - k0;
+    if (threadIdx.x == 0) mv[0] = 0;
     __syncthreads();
-    trailing_update<NT>(A, lda, n, k0, kend);
+    if (m <= NT)
+      panel_factor<NT, 1>(A, lda, k0, kw, m, pan, inv, red, redi, ipiv, mv, info);
+    else
+      panel_factor<NT, 2>(A, lda, k0, kw, m, pan, inv, red, redi, ipiv, mv, info);
+    if (threadIdx.x < kw) piv[k0 + threadIdx.x] = k0 + ipiv[threadIdx.x];
+    __syncthreads();
+    // the moved rows of every other column: each wave owns a tile of
+    // nm rows x cw columns per round and issues all of the tile's loads
+    // before its stores (a wave executes in order, so no barrier is needed)
+    {
+      const int nm = mv[0];
+      if (nm > 0) {
+        constexpr int MV_U = 8, NW = NT / 64;
+        const int lgcw = 9 - (nm > 1 ? 32 - __clz(nm - 1) : 0);   // nm * cw <= 64 * MV_U
+        const int cw = 1 << lgcw, ncol = n - kw;
+        const int lane = threadIdx.x & 63;
+        for (int c0 = (threadIdx.x >> 6) * cw; c0 < ncol; c0 += NW * cw) {
+          double v[MV_U];
+#pragma unroll
+          for (int u = 0; u < MV_U; ++u) {
+            const int e = lane + 64 * u, q = e >> lgcw, ci = c0 + (e & (cw - 1));
+            const int col = ci < k0 ? ci : ci + kw;
+            v[u] = (q < nm && ci < ncol) ? A[size_t(k0 + mv[3 + 2 * q]) * lda + col] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < MV_U; ++u) {
+            const int e = lane + 64 * u, q = e >> lgcw, ci = c0 + (e & (cw - 1));
+            const int col = ci < k0 ? ci : ci + kw;
+            if (q < nm && ci < ncol) A[size_t(k0 + mv[2 + 2 * q]) * lda + col] = v[u];
+          }
+        }
+      }
+    }
+    // U12 = L11^{-1} A12 on the matrix cores: lane jc < PW forms column jc
+    // of the inverse of the unit lower 16x16 L11 (identity beyond kw) in
+    // registers, then every 16-column tile of A12 is one 16x16x16 product.
+    if (threadIdx.x < PW) {
+      const int jc = threadIdx.x;
+      double col[PW];
+#pragma unroll
+      for (int r = 0; r < PW; ++r) {
+        double v = r == jc ? 1.0 : 0.0;
+        if (r < kw)
+#pragma unroll
+          for (int q = 0; q < r; ++q)
+            if (q >= jc) v -= pan[r * PW + q] * col[q];
+        col[r] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < PW; ++r) inv[r * PW + jc] = col[r];
+    }
+    __syncthreads();
+    {
+      const int kend = k0 + kw;
+      const int mt = (n - kend + 15) >> 4;
+      const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+      for (int t = threadIdx.x >> 6; t < mt; t += NT / 64) {
+        const int col = kend + 16 * t + li;
+        double bop[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int kc = 4 * kk + lk;
+          bop[kk] = (kc < kw && col < n) ? A[size_t(k0 + kc) * lda + col] : 0.0;
+        }
+        d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(inv[li * PW + 4 * kk + lk], bop[kk], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = lk + 4 * v;
+          if (r < kw && col < n) A[size_t(k0 + r) * lda + col] = acc[v];
+        }
+      }
+    }
+    __syncthreads();
+    trailing_update<NT>(A, lda, n, k0, kw, pan);
     __syncthreads();
   }
+  // permutation from the swap sequence (once per factorisation)
+  if (threadIdx.x == 0) {
+    int *pm = reinterpret_cast<int *>(pan);
+    for (int i = 0; i < n; ++i) pm[i] = i;
+    for (int k = 0; k < n; ++k) {
+      const int p = piv[k];
+      const int t = pm[k];
+      pm[k] = pm[p];
+      pm[p] = t;
+    }
+  }
+  __syncthreads();
+  if (perm)
+    for (int i = threadIdx.x; i < n; i += NT) perm[i] = reinterpret_cast<int *>(pan)[i];
+  __syncthreads();
   return info;
 }
 
-// Solves with the factors of wg_lu: A x = b (trans = false) or A^T x = b.
-// x (LDS) holds b on entry and x on return. The triangular solves run in
-// blocks of SB rows: the diagonal block is staged in LDS (blk, SB*SB
-// doubles) and solved by the first wavefront, then every thread updates
-// the remaining rows with the block's solution.
-constexpr int SB = 32;
-
+// Block of the triangular solves: rows [b0, b0+bs), the diagonal block
+// staged in LDS (row stride SBP, zero beyond bs) and solved by the first
+// wavefront (lane = row). In the chains below each step's operand comes
+// from registers loaded 16 at a time, and the lane holding the newest
+// unknown hands it to the others through a scalar register.
 template <int NT>
-__device__ void wg_solve(const double *__restrict__ LU, int lda, int n,
-                         const int *__restrict__ piv, double *x, bool trans, double *blk) {
+__device__ __forceinline__ void stage_block(const double *LU, int lda, int b0, int bs, double *blk) {
+  constexpr int U = (SB * SB) / NT;   // every load of the block in flight at once
+  double v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * NT, r = e / SB, q = e - r * SB;
+    v[u] = (r < bs && q < bs) ? LU[size_t(b0 + r) * lda + b0 + q] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * NT, r = e / SB, q = e - r * SB;
+    blk[r * SBP + q] = v[u];
+  }
+}
+
+// out[i] -= sum_{q < bs} M(i, q) x[b0 + q] with M(i, q) = rowmajor ?
+// LU[i][b0+q] : LU[b0+q][i], for i in [i0, i1). Row-major: four lanes
+// share a row (interleaved columns, so a quad reads 32 contiguous bytes),
+// reduced with shuffles. Column-major: one lane per row, so a wave reads
+// contiguous rows. All 16 loads of a lane are in flight together.
+template <int NT, bool ROWMAJOR>
+__device__ __forceinline__ void block_gemv(const double *LU, int lda, int b0, int bs, int i0, int i1,
+                                           double *x) {
+  if constexpr (ROWMAJOR) {
+    const int sub = threadIdx.x & 3;
+    for (int base = i0; base < i1; base += NT / 4) {
+      const int i = base + (threadIdx.x >> 2);
+      const bool ok = i < i1;
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int q = 4 * u + sub;
+        v[u] = (ok && q < bs) ? LU[size_t(i) * lda + b0 + q] : 0.0;
+      }
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int q = 4 * u + sub;
+        s += v[u] * (q < bs ? x[b0 + q] : 0.0);
+      }
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
+      if (ok && sub == 0) x[i] -= s;
+    }
+  } else {
+    for (int i = i0 + threadIdx.x; i < i1; i += NT) {
+      double s = 0.0;
+      for (int q0 = 0; q0 < bs; q0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          v[u] = q0 + u < bs ? LU[size_t(b0 + q0 + u) * lda + i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += v[u] * (q0 + u < bs ? x[b0 + q0 + u] : 0.0);
+      }
+      x[i] -= s;
+    }
+  }
+}
+
+// Solves with the factors of wg_lu: A x = b (trans = false) or A^T x = b.
+// x (LDS, n doubles) holds b on entry and x on return; tmp (LDS, n
+// doubles) is scratch; blk: SB*SBP doubles of LDS.
+template <int NT>
+__device__ __forceinline__ void wg_solve(const double *__restrict__ LU, int lda, int n,
+                         const int *__restrict__ perm, double *x, double *tmp, bool trans,
+                         double *blk) {
   const int lane = threadIdx.x & 63;
   const bool w0 = threadIdx.x < 64;
   if (!trans) {
-    if (threadIdx.x == 0)
-      for (int k = 0; k < n; ++k) {
-        const int p = piv[k];
-        if (p != k) {
-          const double t = x[k];
-          x[k] = x[p];
-          x[p] = t;
-        }
-      }
+    for (int i = threadIdx.x; i < n; i += NT) tmp[i] = x[perm[i]];
     __syncthreads();
+    for (int i = threadIdx.x; i < n; i += NT) x[i] = tmp[i];
     // L y = P b, L unit lower
     for (int b0 = 0; b0 < n; b0 += SB) {
       const int bs = b0 + SB < n ? SB : n - b0;
-      for (int e = threadIdx.x; e < bs * bs; e += NT)
-        blk[e] = LU[size_t(b0 + e / bs) * lda + b0 + e % bs];
+      stage_block<NT>(LU, lda, b0, bs, blk);
       __syncthreads();
       if (w0) {
         double xr = lane < bs ? x[b0 + lane] : 0.0;
-        for (int q = 0; q < bs - 1; ++q) {
-          const double xq = __shfl(xr, q);
-          if (lane > q && lane < bs) xr -= blk[lane * bs + q] * xq;
+        for (int q0 = 0; q0 < bs - 1; q0 += 16) {
+          double o[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) o[u] = blk[lane * SBP + q0 + u];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            if (q0 + u < bs - 1) {
+              const double xq = bcast(xr, q0 + u);
+              if (lane > q0 + u) xr -= o[u] * xq;
+            }
+          }
         }
         if (lane < bs) x[b0 + lane] = xr;
       }
       __syncthreads();
-      for (int i = b0 + bs + threadIdx.x; i < n; i += NT) {
-        const double *Li = LU + size_t(i) * lda + b0;
-        double s = 0.0;
-        for (int q = 0; q < bs; ++q) s += Li[q] * x[b0 + q];
-        x[i] -= s;
-      }
+      block_gemv<NT, true>(LU, lda, b0, bs, b0 + bs, n, x);
       __syncthreads();
     }
-    // U x = y
+    // U x = y; the unknown of row q is scaled by 1/U(q,q), formed up front
     for (int bend = n; bend > 0; bend -= SB) {
       const int b0 = bend - SB > 0 ? bend - SB : 0, bs = bend - b0;
-      for (int e = threadIdx.x; e < bs * bs; e += NT)
-        blk[e] = LU[size_t(b0 + e / bs) * lda + b0 + e % bs];
+      stage_block<NT>(LU, lda, b0, bs, blk);
       __syncthreads();
       if (w0) {
         double xr = lane < bs ? x[b0 + lane] : 0.0;
-        for (int q = bs - 1; q >= 0; --q) {
-          if (lane == q) xr = xr / blk[q * bs + q];
-          const double xq = __shfl(xr, q);
-          if (lane < q) xr -= blk[lane * bs + q] * xq;
+        const double rd = lane < bs ? 1.0 / blk[lane * SBP + lane] : 0.0;
+        for (int q1 = bs; q1 > 0; q1 -= 16) {   // steps q = q1-1 .. q1-16
+          double o[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) o[u] = q1 - 1 - u >= 0 ? blk[lane * SBP + q1 - 1 - u] : 0.0;
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int q = q1 - 1 - u;
+            if (q >= 0) {
+              if (lane == q) xr *= rd;
+              const double xq = bcast(xr, q);
+              if (lane < q) xr -= o[u] * xq;
+            }
+          }
         }
         if (lane < bs) x[b0 + lane] = xr;
       }
       __syncthreads();
-      for (int i = threadIdx.x; i < b0; i += NT) {
-        const double *Ui = LU + size_t(i) * lda + b0;
-        double s = 0.0;
-        for (int q = 0; q < bs; ++q) s += Ui[q] * x[b0 + q];
-        x[i] -= s;
-      }
+      block_gemv<NT, true>(LU, lda, b0, bs, 0, b0, x);
       __syncthreads();
     }
   } else {
     // U^T z = b (lower, diagonal of U)
     for (int b0 = 0; b0 < n; b0 += SB) {
       const int bs = b0 + SB < n ? SB : n - b0;
-      for (int e = threadIdx.x; e < bs * bs; e += NT)
-        blk[e] = LU[size_t(b0 + e / bs) * lda + b0 + e % bs];
+      stage_block<NT>(LU, lda, b0, bs, blk);
       __syncthreads();
       if (w0) {
         double xr = lane < bs ? x[b0 + lane] : 0.0;
-        for (int q = 0; q < bs; ++q) {
-          if (lane == q) xr = xr / blk[q * bs + q];
-          const double xq = __shfl(xr, q);
-          if (lane > q && lane < bs) xr -= blk[q * bs + lane] * xq;
+        const double rd = lane < bs ? 1.0 / blk[lane * SBP + lane] : 0.0;
+        for (int q0 = 0; q0 < bs; q0 += 16) {
+          double o[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) o[u] = blk[(q0 + u) * SBP + lane];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int q = q0 + u;
+            if (q < bs) {
+              if (lane == q) xr *= rd;
+              const double xq = bcast(xr, q);
+              if (lane > q && lane < bs) xr -= o[u] * xq;
+            }
+          }
         }
         if (lane < bs) x[b0 + lane] = xr;
       }
       __syncthreads();
-      for (int i = b0 + bs + threadIdx.x; i < n; i += NT) {
-        double s = 0.0;
-        for (int q = 0; q < bs; ++q) s += LU[size_t(b0 + q) * lda + i] * x[b0 + q];
-        x[i] -= s;
-      }
+      block_gemv<NT, false>(LU, lda, b0, bs, b0 + bs, n, x);
       __syncthreads();
     }
     // L^T w = z (upper, unit diagonal)
     for (int bend = n; bend > 0; bend -= SB) {
       const int b0 = bend - SB > 0 ? bend - SB : 0, bs = bend - b0;
-      for (int e = threadIdx.x; e < bs * bs; e += NT)
-        blk[e] = LU[size_t(b0 + e / bs) * lda + b0 + e % bs];
+      stage_block<NT>(LU, lda, b0, bs, blk);
       __syncthreads();
       if (w0) {
         double xr = lane < bs ? x[b0 + lane] : 0.0;
-        for (int q = bs - 1; q > 0; --q) {
-          const double xq = __shfl(xr, q);
-          if (lane < q) xr -= blk[q * bs + lane] * xq;
+        for (int q1 = bs; q1 > 1; q1 -= 16) {   // steps q = q1-1 .. max(1, q1-16)
+          double o[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) o[u] = q1 - 1 - u >= 1 ? blk[(q1 - 1 - u) * SBP + lane] : 0.0;
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int q = q1 - 1 - u;
+            if (q >= 1) {
+              const double xq = bcast(xr, q);
+              if (lane < q) xr -= o[u] * xq;
+            }
+          }
         }
         if (lane < bs) x[b0 + lane] = xr;
       }
       __syncthreads();
-      for (int i = threadIdx.x; i < b0; i += NT) {
-        double s = 0.0;
-        for (int q = 0; q < bs; ++q) s += LU[size_t(b0 + q) * lda + i] * x[b0 + q];
-        x[i] -= s;
-      }
+      block_gemv<NT, false>(LU, lda, b0, bs, 0, b0, x);
       __syncthreads();
     }
-    // x = P^T w: swaps in reverse order
-    if (threadIdx.x == 0)
-      for (int k = n - 1; k >= 0; --k) {
-        const int p = piv[k];
-        if (p != k) {
-          const double t = x[k];
-          x[k] = x[p];
-          x[p] = t;
-        }
-      }
+    // x = P^T w: x[perm[i]] = w[i]
+    for (int i = threadIdx.x; i < n; i += NT) tmp[perm[i]] = x[i];
     __syncthreads();
+    for (int i = threadIdx.x; i < n; i += NT) x[i] = tmp[i];
   }
+  __syncthreads();
 }
 
 }  // namespace ac

@@ -44,6 +44,14 @@ __device__ __forceinline__ double pow_neg(double x, double e) {
   return x == 0.0 ? INFINITY : pow(x, -e);
 }
 
+// One LDS region serves, at different times, the RHS rate block and its
+// partial-sum slots, the LU panel, and the solves' diagonal block.
+__host__ __device__ inline int bdf_scratch_doubles(const DNet &n) {
+  const int rhs = n.nr + (n.rhs.n_slot > 0 ? n.rhs.n_slot : 1);
+  const int la = la_scratch_doubles(n.ns);
+  return rhs > la ? rhs : la;
+}
+
 // Per-workgroup view of one cell's work.
 struct CellCtx {
   const DNet *n;
@@ -52,10 +60,11 @@ struct CellCtx {
   double *tailp;   // Jacobian tail partials (slot, global)
   double *M;       // Newton matrix / LU (slot, global)
   int *piv;        // pivots (slot, global)
+  int *perm;       // row permutation of the factorisation (slot, global)
   double *D;       // difference array [NDROW][ns] (slot, global)
   int lda;
-  double *rs, *part, *blk, *red;   // LDS scratch
-  int *redi;
+  double *rs, *part, *scr, *tmp, *red;   // LDS: rate block + slots | LU panel | solve block
+  int *redi, *ipiv;
   int cnt[ST_N];   // per-cell counters (identical on every thread)
 };
 
@@ -77,9 +86,24 @@ __device__ __forceinline__ bool wg_any(bool b, double *red) {
 
 // f = S R(y) with the cell's coefficients; y and f in LDS.
 template <int NT>
-__device__ void cell_rhs(CellCtx &cx, const double *y, double *f) {
+__device__ __forceinline__ void cell_rhs(CellCtx &cx, const double *y, double *f) {
   const DNet &n = *cx.n;
-  for (int j = threadIdx.x; j < n.nr; j += NT) cx.rs[j] = reaction_rate(n.rpair[j], cx.kg[j], y);
+  constexpr int U = 4;
+  for (int j0 = threadIdx.x; j0 < n.nr; j0 += U * NT) {
+    uint32_t pr[U];
+    double kv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * NT;
+      pr[u] = j < n.nr ? n.rpair[j] : 0u;
+      kv[u] = j < n.nr ? cx.kg[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * NT;
+      if (j < n.nr) cx.rs[j] = reaction_rate(pr[u], kv[u], y);
+    }
+  }
   __syncthreads();
   segsum_chunks<NT, LAYOUT_SELL, false, false>(n.rhs, cx.rs, y, cx.part, f);
   __syncthreads();
@@ -90,17 +114,32 @@ __device__ void cell_rhs(CellCtx &cx, const double *y, double *f) {
 
 // Jacobian values on the pattern at y (LDS) into the slot.
 template <int NT>
-__device__ void cell_jac(CellCtx &cx, const double *y) {
+__device__ __forceinline__ void cell_jac(CellCtx &cx, const double *y) {
   const DNet &n = *cx.n;
   segsum_chunks<NT, LAYOUT_SELL, true, false>(n.jtail, cx.kg, y, cx.tailp, nullptr);
   __syncthreads();
-  for (int e = threadIdx.x; e < n.nnz_j; e += NT) {
-    double acc = term(n.jhead0[e], cx.kg, y);
-    acc = __dadd_rn(acc, term(n.jhead1[e], cx.kg, y));
-    const uint32_t td = n.jtaildesc[e];
-    const int q0 = int(td >> 8), nq = int(td & 255u);
-    for (int q = 0; q < nq; ++q) acc = __dadd_rn(acc, cx.tailp[q0 + q]);
-    cx.Jg[e] = acc;
+  constexpr int EU = 4;
+  for (int e0 = threadIdx.x; e0 < n.nnz_j; e0 += EU * NT) {
+    uint32_t h0[EU], h1[EU], td[EU];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      const int e = e0 + u * NT;
+      const bool ok = e < n.nnz_j;
+      h0[u] = ok ? n.jhead0[e] : 2047u << 16;
+      h1[u] = ok ? n.jhead1[e] : 2047u << 16;
+      td[u] = ok ? n.jtaildesc[e] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      const int e = e0 + u * NT;
+      if (e < n.nnz_j) {
+        double acc = term(h0[u], cx.kg, y);
+        acc = __dadd_rn(acc, term(h1[u], cx.kg, y));
+        const int q0 = int(td[u] >> 8), nq = int(td[u] & 255u);
+        for (int q = 0; q < nq; ++q) acc = __dadd_rn(acc, cx.tailp[q0 + q]);
+        cx.Jg[e] = acc;
+      }
+    }
   }
   __syncthreads();
   cx.cnt[ST_JAC]++;
@@ -108,7 +147,7 @@ __device__ void cell_jac(CellCtx &cx, const double *y) {
 
 // M = I - c J (dense, row-major, lda) from the pattern values, then LU.
 template <int NT>
-__device__ void cell_factor(CellCtx &cx, double c) {
+__device__ __forceinline__ void cell_factor(CellCtx &cx, double c) {
   const DNet &n = *cx.n;
   const int ns = n.ns, lda = cx.lda;
   for (int e = threadIdx.x; e < ns * lda; e += NT) {
@@ -116,21 +155,34 @@ __device__ void cell_factor(CellCtx &cx, double c) {
     cx.M[e] = (i == a) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < n.nnz_j; e += NT) {
-    const int i = n.jent_row[e], a = n.jent_col[e];
-    cx.M[size_t(i) * lda + a] = (i == a ? 1.0 : 0.0) - c * cx.Jg[e];
+  constexpr int EU = 4;
+  for (int e0 = threadIdx.x; e0 < n.nnz_j; e0 += EU * NT) {
+    int ri[EU], ci[EU];
+    double jv[EU];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      const int e = e0 + u * NT;
+      const bool ok = e < n.nnz_j;
+      ri[u] = ok ? n.jent_row[e] : 0;
+      ci[u] = ok ? n.jent_col[e] : 0;
+      jv[u] = ok ? cx.Jg[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < EU; ++u)
+      if (e0 + u * NT < n.nnz_j)
+        cx.M[size_t(ri[u]) * lda + ci[u]] = (ri[u] == ci[u] ? 1.0 : 0.0) - c * jv[u];
   }
   __syncthreads();
-  wg_lu<NT>(cx.M, lda, ns, cx.piv, cx.red, cx.redi);
+  wg_lu<NT>(cx.M, lda, ns, cx.piv, cx.perm, cx.scr, cx.red, cx.redi, cx.ipiv);
   cx.cnt[ST_LU]++;
 }
 
 // Resample D[0..q] for a step change by `factor` (Shampine & Reichelt
 // 1997): D <- (R(factor) U)^T D with U = R(1).
 template <int NT>
-__device__ void rescale_diffs(CellCtx &cx, int q, double factor, int ns) {
+__device__ __forceinline__ void rescale_diffs(CellCtx &cx, int q, double factor, int ns) {
   constexpr int W = QMAX + 1;
-  double *RU = cx.red + 8, *R = RU + W * W, *U = R + W * W;   // LDS
+  double *RU = cx.red + 16, *R = RU + W * W, *U = R + W * W;   // LDS
   if (threadIdx.x == 0) {
     for (int j = 0; j <= q; ++j) {
       R[j] = 1.0;
@@ -182,7 +234,7 @@ __device__ __forceinline__ void tape_put(const TapeView &tv, int64_t cell, int &
 }
 
 template <int NT>
-__global__ __launch_bounds__(NT, 2) void k_bdf(DNet n, const double *__restrict__ la_over,
+__global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ la_over,
                                             int64_t n_cells, double *__restrict__ y,
                                             const double *__restrict__ T, BdfParams P,
                                             CellOut out, TapeView tv, WsView W,
@@ -190,11 +242,11 @@ __global__ __launch_bounds__(NT, 2) void k_bdf(DNet n, const double *__restrict_
   extern __shared__ double sm[];
   const int ns = n.ns, nr = n.nr;
   double *f = sm, *yn = f + ns, *dd = yn + ns, *psi = dd + ns, *scl = psi + ns, *yp = scl + ns,
-         *dy = yp + ns, *rs = dy + ns;
-  double *part = rs + nr;
-  double *blk = part + (n.rhs.n_slot > 0 ? n.rhs.n_slot : 1);
-  double *red = blk + SB * SB;
-  int *redi = reinterpret_cast<int *>(red + 8 + 3 * (QMAX + 1) * (QMAX + 1));
+         *dy = yp + ns, *tmp = dy + ns, *scr = tmp + ns;
+  double *rs = scr, *part = scr + nr;        // RHS use of the scratch region
+  double *red = scr + bdf_scratch_doubles(n);
+  int *redi = reinterpret_cast<int *>(red + 16 + 3 * (QMAX + 1) * (QMAX + 1));
+  int *ipiv = redi + 16;
   __shared__ int64_t s_cell;
 
   const size_t slot = blockIdx.x;
@@ -205,13 +257,16 @@ __global__ __launch_bounds__(NT, 2) void k_bdf(DNet n, const double *__restrict_
   cx.tailp = W.tail + slot * W.tail_stride;
   cx.M = W.M + slot * W.m_stride;
   cx.piv = W.piv + slot * W.piv_stride;
+  cx.perm = cx.piv + ns;
   cx.D = W.D + slot * W.d_stride;
   cx.lda = W.lda;
   cx.rs = rs;
   cx.part = part;
-  cx.blk = blk;
+  cx.scr = scr;
+  cx.tmp = tmp;
   cx.red = red;
   cx.redi = redi;
+  cx.ipiv = ipiv;
   const double rtol = P.rtol, atol = P.atol, t_end = P.t_end;
   const double tol = fmax(10.0 * 2.220446049250313e-16 / rtol, fmin(0.03, sqrt(rtol)));
 
@@ -341,7 +396,7 @@ __global__ __launch_bounds__(NT, 2) void k_bdf(DNet n, const double *__restrict_
               if (wg_any<NT>(nonfinite, red)) break;
               for (int x = threadIdx.x; x < ns; x += NT) dy[x] = c * f[x] - psi[x] - dd[x];
               __syncthreads();
-              wg_solve<NT>(cx.M, cx.lda, ns, cx.piv, dy, false, blk);
+              wg_solve<NT>(cx.M, cx.lda, ns, cx.perm, dy, cx.tmp, false, cx.scr);
               const double dn = wg_rms<NT>(dy, 1.0, scl, ns, red);
               double rate = 0.0;
               if (it > 0) {
@@ -447,10 +502,13 @@ __global__ void k_reset_queue(unsigned *q) {
 template <int NT>
 __global__ __launch_bounds__(NT) void k_lu_factor(int n, int lda, int64_t nmat, double *A,
                                                   int *piv, int *info) {
+  extern __shared__ double sm[];
   __shared__ double red[NT / 64];
   __shared__ int redi[NT / 64];
+  __shared__ int ipiv[9 * PW + 2];
   for (int64_t m = blockIdx.x; m < nmat; m += gridDim.x) {
-    const int inf = wg_lu<NT>(A + size_t(m) * n * lda, lda, n, piv + size_t(m) * n, red, redi);
+    int *pm = piv + size_t(m) * n;
+    const int inf = wg_lu<NT>(A + size_t(m) * n * lda, lda, n, pm, nullptr, sm, red, redi, ipiv);
     if (threadIdx.x == 0 && info) info[m] = inf;
     __syncthreads();
   }
@@ -460,12 +518,22 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_lu_solve(int n, int lda, int64_t nmat, const double *LU,
                                                  const int *piv, double *b, int trans) {
   extern __shared__ double sm[];
-  double *x = sm, *blk = sm + n;
+  double *x = sm, *tmp = sm + n, *blk = tmp + n;
+  int *perm = reinterpret_cast<int *>(blk + SB * SBP);
   for (int64_t m = blockIdx.x; m < nmat; m += gridDim.x) {
+    const int *pv = piv + size_t(m) * n;
+    if (threadIdx.x == 0) {
+      for (int i = 0; i < n; ++i) perm[i] = i;
+      for (int k = 0; k < n; ++k) {
+        const int p = pv[k], t = perm[k];
+        perm[k] = perm[p];
+        perm[p] = t;
+      }
+    }
     double *bm = b + size_t(m) * n;
     for (int i = threadIdx.x; i < n; i += NT) x[i] = bm[i];
     __syncthreads();
-    wg_solve<NT>(LU + size_t(m) * n * lda, lda, n, piv + size_t(m) * n, x, trans != 0, blk);
+    wg_solve<NT>(LU + size_t(m) * n * lda, lda, n, perm, x, tmp, trans != 0, blk);
     for (int i = threadIdx.x; i < n; i += NT) bm[i] = x[i];
     __syncthreads();
   }
@@ -474,9 +542,8 @@ __global__ __launch_bounds__(NT) void k_lu_solve(int n, int lda, int64_t nmat, c
 // ---------------------------------------------------------------- launch
 
 size_t bdf_lds_bytes(const DNet &n) {
-  return sizeof(double) * (size_t(7) * n.ns + n.nr + (n.rhs.n_slot > 0 ? n.rhs.n_slot : 1) +
-                           SB * SB + 8 + 3 * (QMAX + 1) * (QMAX + 1)) +
-         sizeof(int) * 8;
+  return sizeof(double) * (size_t(8) * n.ns + bdf_scratch_doubles(n) + 16 + 3 * (QMAX + 1) * (QMAX + 1)) +
+         sizeof(int) * (16 + 9 * PW + 2);
 }
 
 int bdf_resident_blocks(const DNet &n) {
@@ -511,7 +578,10 @@ hipError_t launch_lu_factor(int n, int lda, int64_t nmat, double *A, int *piv, i
                             hipStream_t st) {
   if (nmat == 0) return hipSuccess;
   const int g = int(nmat < 4096 ? nmat : 4096);
-  hipLaunchKernelGGL(k_lu_factor<BDF_NT>, dim3(g), dim3(BDF_NT), 0, st, n, lda, nmat, A, piv, info);
+  const size_t lds = sizeof(double) * size_t(la_scratch_doubles(n));
+  if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(k_lu_factor<BDF_NT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  hipLaunchKernelGGL(k_lu_factor<BDF_NT>, dim3(g), dim3(BDF_NT), lds, st, n, lda, nmat, A, piv, info);
   return hipGetLastError();
 }
 
@@ -519,7 +589,7 @@ hipError_t launch_lu_solve(int n, int lda, int64_t nmat, const double *LU, const
                            double *b, int trans, hipStream_t st) {
   if (nmat == 0) return hipSuccess;
   const int g = int(nmat < 4096 ? nmat : 4096);
-  const size_t lds = sizeof(double) * (size_t(n) + SB * SB);
+  const size_t lds = sizeof(double) * (size_t(2) * n + SB * SBP) + sizeof(int) * size_t(n);
   if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(k_lu_solve<BDF_NT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   hipLaunchKernelGGL(k_lu_solve<BDF_NT>, dim3(g), dim3(BDF_NT), lds, st, n, lda, nmat, LU, piv, b,

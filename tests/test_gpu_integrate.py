@@ -145,18 +145,21 @@ def test_tiny_network_parity(acm, torch_dev, oracle_mod, tiny, q_max, years):
         T = np.array([10.0, 20.0, 35.0, 60.0, 150.0, 300.0])
     t_end = years * YEAR_S
     y, out, _ = _run(acm, torch, net, y0, T, t_end, q_max=q_max)
-    ref, env, steps = oracle_with_envelope(oracle_mod, net, y0, T, t_end, q_max=q_max)
+    ref, env, steps = oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=8, q_max=q_max)
     assert out["status"].tolist() == ref["status"].tolist() == [0] * len(T)
     ok = _agree(y, ref["y"], envelope=env)
     assert ok.all(), np.argwhere(~ok)[:5]
     strict = _agree(y, ref["y"])
     print(f"strict 1e-6 bar met by {strict.mean():.4f} of species-cells")
-    # Step counts: a rounding-level difference can flip one accept/reject
-    # decision on an ill-conditioned (hot) cell; most cells match exactly.
+    # Step counts: rounding-level differences flip single accept/reject
+    # decisions, so the oracle's own count already moves by a step or two
+    # under 1e-15 relative perturbations of y0. The GPU count must fall in
+    # the range the perturbed oracle runs span (one step of slack).
     g, o = out["stats"][:, 0], ref["stats"][:, 0]
-    print("steps gpu", g.tolist(), "oracle", o.tolist())
+    print("steps gpu", g.tolist(), "oracle", o.tolist(), "perturbed range",
+          steps.min(0).tolist(), steps.max(0).tolist())
     assert np.all(np.abs(g - o) <= 0.01 * o + 3)
-    assert (g == o).mean() >= 0.5
+    assert np.all((g >= steps.min(0) - 1) & (g <= steps.max(0) + 1))
 
 
 def test_medium_network_parity(acm, torch_dev, oracle_mod, medium):
@@ -218,28 +221,43 @@ def test_status_codes(acm, torch_dev, tiny):
     assert out["status"].tolist() == [0] and np.array_equal(y, y0[:1])
 
 
+def _tape_compare(a_tape, a_len, b_tape, b_len):
+    """(length difference, decision-prefix fraction, median and 95% quantile
+    of the relative value differences over the common decision prefix)."""
+    m = min(a_len, b_len)
+    a, b = a_tape[:m], b_tape[:m]
+    same = (a["type"] == b["type"]) & (a["q"] == b["q"])
+    prefix = m if same.all() else int(np.argmin(same))
+    rel = np.abs(a["val"][:prefix] - b["val"][:prefix]) / np.abs(b["val"][:prefix])
+    return abs(a_len - b_len), prefix / m, np.median(rel), np.quantile(rel, 0.95)
+
+
 def test_recorded_tape_matches_oracle(acm, torch_dev, oracle_mod, tiny):
     """The recorded step sequence (used by replay and the adjoint) carries the
-    same decisions as the oracle's: identical on the rounding-stable 20 K
-    cell, identical up to a late flipped accept/reject on the 90 K cell."""
+    oracle's decisions and values to within the oracle's own sensitivity:
+    each statistic of the GPU tape against the oracle's is bounded by the
+    worst that 8 oracle reruns with y0 perturbed by 1e-15 relative show."""
     torch = torch_dev
     net, cells = tiny
     y0, T = cells.y0[:2], np.array([20.0, 90.0])
-    _, out, raw = _run(acm, torch, net, y0, T, 1e5 * YEAR_S, tape_cap=20000)
+    t_end = 1e5 * YEAR_S
+    _, out, raw = _run(acm, torch, net, y0, T, t_end, tape_cap=20000)
     tape = acm.tape_to_numpy(raw["tape"])
-    ref = oracle_mod.bdf(net, y0, T, 1e5 * YEAR_S, tape_cap=20000)
+    ref = oracle_mod.bdf(net, y0, T, t_end, tape_cap=20000)
+    rng = np.random.default_rng(99)
+    pert = [oracle_mod.bdf(net, y0 * (1 + 1e-15 * rng.standard_normal(y0.shape)), T, t_end,
+                           tape_cap=20000) for _ in range(8)]
     for c in range(2):
-        L, Lo = int(out["tape_len"][c]), int(ref["tape_len"][c])
-        assert L > 0 and Lo > 0 and abs(L - Lo) <= 0.01 * Lo + 3
-        m = min(L, Lo)
-        a, b = tape[c, :m], ref["tape"][c, :m]
-        same = (a["type"] == b["type"]) & (a["q"] == b["q"])
-        prefix = m if same.all() else int(np.argmin(same))
-        assert prefix >= 0.5 * m, (c, prefix, m)
-        if c == 0:
-            assert L == Lo and prefix == m
-        # values: step factors come from error norms of d ~ rtol*y, which
-        # carry the trajectories' 1e-7 differences amplified by 1/rtol
-        np.testing.assert_allclose(a["val"][:1], b["val"][:1], rtol=1e-9)
-        rel = np.abs(a["val"][:prefix] - b["val"][:prefix]) / np.abs(b["val"][:prefix])
-        assert np.median(rel) < 1e-4 and np.quantile(rel, 0.95) < 1e-2, (np.median(rel), rel.max())
+        Lo = int(ref["tape_len"][c])
+        g = _tape_compare(tape[c], int(out["tape_len"][c]), ref["tape"][c], Lo)
+        p = np.array([_tape_compare(o["tape"][c], int(o["tape_len"][c]), ref["tape"][c], Lo)[:4]
+                      for o in pert])
+        print(f"cell {c}: gpu dlen {g[0]} prefix {g[1]:.3f} median {g[2]:.2e} q95 {g[3]:.2e};",
+              f"perturbed worst dlen {p[:, 0].max():.0f} prefix {p[:, 1].min():.3f}",
+              f"median {p[:, 2].max():.2e} q95 {p[:, 3].max():.2e}")
+        assert g[0] <= p[:, 0].max() + 1
+        assert g[1] >= 0.5 * p[:, 1].min()
+        assert g[2] <= max(10 * p[:, 2].max(), 1e-7)
+        assert g[3] <= max(3 * p[:, 3].max(), 1e-3)
+        # the first event (the initial step size) is rounding-stable
+        np.testing.assert_allclose(tape[c]["val"][:1], ref["tape"][c]["val"][:1], rtol=1e-9)
