@@ -55,7 +55,8 @@ typedef enum {
   AC_CELL_OK = 0,
   AC_CELL_MAXSTEPS = 1,   /* step budget exhausted before t_end */
   AC_CELL_HMIN = 2,       /* step size fell below 10 ulp(t) */
-  AC_CELL_BADINPUT = 3    /* T <= 0 or not finite, or an initial density < 0 or not finite */
+  AC_CELL_BADINPUT = 3,   /* T <= 0 or not finite, or an initial density < 0 or not finite */
+  AC_CELL_TAPE = 4        /* adjoint: the cell's tape overflowed or is malformed */
 } ac_cell_status;
 
 /* Storage of S used by the RHS kernel (Sec. 2.2 compares COO, CCS, CRS and
@@ -257,6 +258,41 @@ ac_status ac_integrate(ac_ws *ws, const double *log_alpha, int64_t n_cells, doub
 ac_status ac_integrate_plain(ac_ws *ws, const double *log_alpha, int64_t n_cells, double *y,
                              const double *T, double t_end, const ac_integ_opts *opts,
                              int32_t *cell_status, int32_t *cell_stats, ac_stream stream);
+
+/* Discrete adjoint of ac_integrate for L = sum_c <lambda_c, y_c(t_end)>.
+ * The map differentiated is the recorded step sequence (tape, tape_len as
+ * written by ac_integrate with the same y0, T, log_alpha and tolerances)
+ * with step sizes and orders held fixed and every corrector equation
+ * d - c f(y_pred + d) + psi = 0 solved to convergence, so each accepted
+ * step is differentiated through the implicit function theorem: one
+ * transposed solve with M = I - c J(y_{n+1}), refactored at the converged
+ * state, and one vector-Jacobian product per step. The tape is replayed
+ * forward once, keeping the difference array every 64 accepted steps, and
+ * each 64-step segment is recomputed from its checkpoint during the
+ * reverse sweep. Not in the paper; the forward method is Sec. 3's BDF
+ * integration of eq. matrix-form.
+ *   y0, lambda [n_cells][n_species], T [n_cells]    DEVICE, read
+ *   tape [n_cells][tape_cap], tape_len [n_cells]    DEVICE, read
+ *   y_final [n_cells][n_species] DEVICE or NULL: the replayed y(t_end)
+ *   dL_dy0 [n_cells][n_species] DEVICE, written
+ *   g_cells [n_cells][n_reactions] DEVICE or NULL: per-cell dL/dlog alpha
+ *   dL_dlogalpha [n_reactions] DEVICE or NULL: sum of g_cells over cells in
+ *     cell order (bitwise reproducible); needs g_cells
+ *   cell_status [n_cells] DEVICE or NULL: AC_CELL_OK, AC_CELL_BADINPUT
+ *     (dL_dy0 = lambda, no parameter terms) or AC_CELL_TAPE (tape_len < 0,
+ *     > tape_cap, or an order outside 1..5; dL_dy0 = lambda).
+ * Only rtol and atol of opts are used (they scale the replay's convergence
+ * test). The workspace grows its checkpoint store on the first call with a
+ * larger tape_cap (a device allocation, after synchronising the stream);
+ * about 64 tape_cap n_species bytes per slot. Errors: AC_EINVAL for bad
+ * sizes or NULL required arrays, AC_ENOMEM/AC_EHIP for allocation or
+ * launch failures. */
+ac_status ac_integrate_adjoint(ac_ws *ws, const double *log_alpha, int64_t n_cells,
+                               const double *y0, const double *T, const ac_integ_opts *opts,
+                               const ac_event *tape, int32_t tape_cap, const int32_t *tape_len,
+                               const double *lambda, double *y_final, double *dL_dy0,
+                               double *g_cells, double *dL_dlogalpha, int32_t *cell_status,
+                               ac_stream stream);
 
 /* Status text and the calling thread's last error message (incl. HIP's). */
 const char *ac_status_string(ac_status s);

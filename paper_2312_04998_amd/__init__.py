@@ -21,7 +21,7 @@ AC_OK, AC_EINVAL, AC_ENOMEM, AC_EHIP, AC_EUNBALANCED, AC_ECAPACITY, AC_ELIMIT = 
 AC_LAYOUT_CSR, AC_LAYOUT_SELL, AC_LAYOUT_COO = 0, 1, 2
 AC_ORDER_NATURAL, AC_ORDER_NNZ_DESC, AC_ORDER_RCM = 0, 1, 2
 AC_FMT_COO, AC_FMT_CCS, AC_FMT_CRS, AC_FMT_SELL = 0, 1, 2, 3
-AC_CELL_OK, AC_CELL_MAXSTEPS, AC_CELL_HMIN, AC_CELL_BADINPUT = 0, 1, 2, 3
+AC_CELL_OK, AC_CELL_MAXSTEPS, AC_CELL_HMIN, AC_CELL_BADINPUT, AC_CELL_TAPE = 0, 1, 2, 3, 4
 LAYOUTS = {"csr": AC_LAYOUT_CSR, "sell": AC_LAYOUT_SELL, "coo": AC_LAYOUT_COO}
 ORDERINGS = {"natural": AC_ORDER_NATURAL, "nnz": AC_ORDER_NNZ_DESC, "rcm": AC_ORDER_RCM}
 
@@ -78,6 +78,8 @@ def _load() -> C.CDLL:
         "ac_ws_info": [vp, vp, vp],
         "ac_integrate": [vp, vp, i64, vp, vp, d, vp, vp, vp, vp, i32, vp, vp],
         "ac_integrate_plain": [vp, vp, i64, vp, vp, d, vp, vp, vp, vp],
+        "ac_integrate_adjoint": [vp, vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
+                                 vp],
     }
     for name, args in sig2.items():
         f = getattr(L, name)
@@ -384,7 +386,108 @@ class Workspace:
         return out
 
 
+    def adjoint(self, y0, T, tape, tape_len, lam, rtol=1e-6, atol=1e-20, log_alpha=None,
+                want_glog=True, want_cells=False, want_y=False, stream=None):
+        """Discrete adjoint (ac_integrate_adjoint) of L = sum <lam, y(t_end)>
+        over the recorded tape of an earlier integrate(..., tape_cap=...).
+        Returns dict of device tensors: dL_dy0 [n, ns], status [n] and, as
+        requested, dL_dlogalpha [nr] (summed over cells in cell order),
+        g_cells [n, nr] and the replayed y_final [n, ns]."""
+        import torch
+        n, ns, nr = T.shape[0], self.net.n_species, self.net.n_reactions
+        _check_dev(T, (n,), "T")
+        _check_dev(y0, (n, ns), "y0")
+        _check_dev(lam, (n, ns), "lam")
+        if log_alpha is not None:
+            _check_dev(log_alpha, (nr,), "log_alpha")
+        if tape.dim() != 3 or tape.shape[0] != n or tape.shape[2] != 2 or not tape.is_contiguous():
+            raise ValueError("tape must be the [n, tape_cap, 2] tensor returned by integrate")
+        if tape_len.dtype != torch.int32 or tuple(tape_len.shape) != (n,):
+            raise ValueError("tape_len must be int32 [n]")
+        dev = y0.device
+        gy0 = torch.empty_like(y0)
+        status = torch.empty(n, dtype=torch.int32, device=dev)
+        out = {"dL_dy0": gy0, "status": status}
+        g_cells = glog = yf = None
+        if want_glog or want_cells:
+            g_cells = torch.empty((n, nr), dtype=torch.float64, device=dev)
+            if want_cells:
+                out["g_cells"] = g_cells
+        if want_glog:
+            glog = torch.empty(nr, dtype=torch.float64, device=dev)
+            out["dL_dlogalpha"] = glog
+        if want_y:
+            yf = torch.empty_like(y0)
+            out["y_final"] = yf
+        o = IntegOpts(float(rtol), float(atol), 0.0, 5, 1)
+        check(lib.ac_integrate_adjoint(self.handle, _ptr(log_alpha), n, _ptr(y0), _ptr(T),
+                                       C.byref(o), _ptr(tape), int(tape.shape[1]),
+                                       _ptr(tape_len), _ptr(lam), _ptr(yf), _ptr(gy0),
+                                       _ptr(g_cells), _ptr(glog), _ptr(status),
+                                       _stream(stream)), "ac_integrate_adjoint")
+        return out
+
+
 def tape_to_numpy(tape_tensor):
     """Device tape tensor -> numpy structured array of EVENT_DTYPE."""
     raw = tape_tensor.cpu().numpy()
     return raw.view(np.uint8).reshape(raw.shape[0], raw.shape[1], 16).copy().view(EVENT_DTYPE)[..., 0]
+
+
+def tape_from_numpy(events, device="cuda"):
+    """numpy structured array of EVENT_DTYPE [n, cap] -> device tape tensor
+    [n, cap, 2] in the layout ac_integrate writes."""
+    import torch
+    ev = np.ascontiguousarray(events, EVENT_DTYPE)
+    raw = ev.view(np.uint8).reshape(ev.shape[0], ev.shape[1], 16).view(np.float64)
+    return torch.from_numpy(raw.copy()).to(device)
+
+
+class Integrate:
+    """y(t_end) = integrate(log_alpha, y0) with a discrete-adjoint backward.
+
+    ``Integrate.apply(log_alpha, y0, T, ws, t_end, opts)`` runs the batched
+    integrator (recording the step sequence) and returns y(t_end); its
+    backward replays that sequence through ac_integrate_adjoint and returns
+    dL/dlog_alpha (summed over cells) and dL/dy0. opts: dict with rtol,
+    atol, q_max, max_steps, tape_cap (events kept per cell)."""
+
+    @staticmethod
+    def apply(log_alpha, y0, T, ws, t_end, opts=None):
+        return _integrate_fn().apply(log_alpha, y0, T, ws, t_end, opts or {})
+
+
+_FN = None
+
+
+def _integrate_fn():
+    global _FN
+    if _FN is not None:
+        return _FN
+    import torch
+
+    class _Integrate(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, log_alpha, y0, T, ws, t_end, opts):
+            rtol = opts.get("rtol", 1e-6)
+            atol = opts.get("atol", 1e-20)
+            cap = opts.get("tape_cap", 2 * opts.get("max_steps", 100000) + 16)
+            y = y0.detach().clone().contiguous()
+            la = log_alpha.detach().contiguous()
+            res = ws.integrate(y, T, t_end, rtol=rtol, atol=atol, q_max=opts.get("q_max", 5),
+                               max_steps=opts.get("max_steps", 100000), log_alpha=la,
+                               tape_cap=cap)
+            ctx.ws, ctx.rtol, ctx.atol = ws, rtol, atol
+            ctx.tape, ctx.tape_len, ctx.status = res["tape"], res["tape_len"], res["status"]
+            ctx.save_for_backward(la, y0.detach().contiguous(), T)
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            la, y0, T = ctx.saved_tensors
+            r = ctx.ws.adjoint(y0, T, ctx.tape, ctx.tape_len, gy.contiguous(), rtol=ctx.rtol,
+                               atol=ctx.atol, log_alpha=la, want_glog=True)
+            return r["dL_dlogalpha"], r["dL_dy0"], None, None, None, None
+
+    _FN = _Integrate
+    return _FN

@@ -417,6 +417,9 @@ struct ac_ws {
   void *buf = nullptr;
   unsigned *queue = nullptr;
   ac::WsView W{};
+  void *adj_buf = nullptr;   // adjoint slots, grown on demand
+  size_t adj_bytes = 0;
+  ac::AdjView A{};
 };
 
 extern "C" {
@@ -492,6 +495,7 @@ ac_status ac_ws_create(const ac_net *net, int32_t n_slots, ac_ws **out) {
 
 ac_status ac_ws_destroy(ac_ws *ws) {
   if (!ws) return AC_OK;
+  if (ws->adj_buf) hipFree(ws->adj_buf);
   hipFree(ws->buf);
   delete ws;
   return AC_OK;
@@ -500,7 +504,7 @@ ac_status ac_ws_destroy(ac_ws *ws) {
 ac_status ac_ws_info(const ac_ws *ws, int32_t *n_slots, int64_t *bytes) {
   if (!ws) return fail(AC_EINVAL, "null workspace");
   if (n_slots) *n_slots = ws->n_slots;
-  if (bytes) *bytes = int64_t(ws->bytes);
+  if (bytes) *bytes = int64_t(ws->bytes + ws->adj_bytes);
   return AC_OK;
 }
 
@@ -543,6 +547,79 @@ ac_status ac_integrate_plain(ac_ws *ws, const double *log_alpha, int64_t n_cells
     hipError_t e = ac::launch_bdf(ws->net->d, log_alpha, 1, y + c * ns, T + c, P, out, tv, ws->W,
                                   nullptr, 1, hipStream_t(stream));
     if (e != hipSuccess) return hip_fail(e, "ac_integrate_plain launch");
+  }
+  return AC_OK;
+}
+
+// Adjoint slots for tapes of up to tape_cap events: checkpoint store
+// (tape_cap / CK_EVERY + 1 difference arrays), one segment of converged
+// states and the adjoint difference array per slot.
+static ac_status adj_reserve(ac_ws *ws, int tape_cap, hipStream_t st) {
+  const int ckcap = tape_cap / ac::CK_EVERY + 1;
+  if (ws->adj_buf && ws->A.ckcap >= ckcap) return AC_OK;
+  const int ns = ws->net->d.ns;
+  auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t dsz = size_t(8) * ns;
+  const size_t db_b = r256(sizeof(double) * dsz);
+  const size_t ck_b = r256(sizeof(double) * dsz * size_t(ckcap));
+  const size_t sy_b = r256(sizeof(double) * size_t(ac::CK_EVERY) * ns);
+  const size_t ce_b = r256(sizeof(int) * size_t(ckcap));
+  const size_t S = size_t(ws->n_slots);
+  const size_t bytes = (db_b + ck_b + sy_b + ce_b) * S;
+  if (ws->adj_buf) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "adjoint workspace resize (sync)");
+    hipFree(ws->adj_buf);
+    ws->adj_buf = nullptr;
+    ws->adj_bytes = 0;
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(adjoint workspace)");
+  ws->adj_buf = p;
+  ws->adj_bytes = bytes;
+  char *b = static_cast<char *>(p);
+  ac::AdjView &A = ws->A;
+  A.Db = reinterpret_cast<double *>(b);
+  b += db_b * S;
+  A.ck = reinterpret_cast<double *>(b);
+  b += ck_b * S;
+  A.segY = reinterpret_cast<double *>(b);
+  b += sy_b * S;
+  A.ckev = reinterpret_cast<int *>(b);
+  A.db_stride = db_b / sizeof(double);
+  A.ck_stride = ck_b / sizeof(double);
+  A.segy_stride = sy_b / sizeof(double);
+  A.ckev_stride = ce_b / sizeof(int);
+  A.ckcap = ckcap;
+  return AC_OK;
+}
+
+ac_status ac_integrate_adjoint(ac_ws *ws, const double *log_alpha, int64_t n_cells,
+                               const double *y0, const double *T, const ac_integ_opts *opts,
+                               const ac_event *tape, int32_t tape_cap, const int32_t *tape_len,
+                               const double *lambda, double *y_final, double *dL_dy0,
+                               double *g_cells, double *dL_dlogalpha, int32_t *cell_status,
+                               ac_stream stream) {
+  if (ac_status s = integ_args(ws, n_cells, y0, T, 0.0, opts)) return s;
+  if (tape_cap <= 0) return fail(AC_EINVAL, "tape_cap must be > 0");
+  if (n_cells && (!tape || !tape_len || !lambda || !dL_dy0))
+    return fail(AC_EINVAL, "null tape, tape_len, lambda or dL_dy0");
+  if (dL_dlogalpha && n_cells && !g_cells)
+    return fail(AC_EINVAL, "dL_dlogalpha needs the per-cell rows g_cells");
+  hipStream_t st = hipStream_t(stream);
+  if (n_cells) {
+    if (ac_status s = adj_reserve(ws, tape_cap, st)) return s;
+    ac::BdfParams P{opts->rtol, opts->atol, opts->h0, 0.0, opts->q_max, opts->max_steps};
+    ac::AdjIO io{reinterpret_cast<const ac::AcEvent *>(tape), tape_len, tape_cap, y0, T, lambda,
+                 y_final, dL_dy0, g_cells, cell_status};
+    hipError_t e = ac::launch_adjoint(ws->net->d, log_alpha, n_cells, io, P, ws->W, ws->A,
+                                      ws->queue, ws->n_slots, st);
+    if (e != hipSuccess) return hip_fail(e, "ac_integrate_adjoint launch");
+  }
+  if (dL_dlogalpha) {
+    hipError_t e = ac::launch_sum_rows(g_cells, n_cells, ws->net->d.nr, dL_dlogalpha, st);
+    if (e != hipSuccess) return hip_fail(e, "ac_integrate_adjoint reduction");
   }
   return AC_OK;
 }

@@ -45,11 +45,38 @@ struct WsView {
   int lda;
 };
 
+// Discrete adjoint: per-slot buffers (checkpoints every CK_EVERY accepted
+// steps, the converged states of one segment, the adjoint difference array).
+constexpr int CK_EVERY = 64;
+
+struct AdjView {
+  double *Db, *ck, *segY;
+  int *ckev;
+  size_t db_stride, ck_stride, segy_stride, ckev_stride;
+  int ckcap;
+};
+
+struct AdjIO {
+  const AcEvent *ev;      // [n_cells][cap]
+  const int32_t *len;     // [n_cells]
+  int cap;
+  const double *y0, *T, *lam;   // [n_cells][ns], [n_cells], [n_cells][ns]
+  double *y_final;        // [n_cells][ns] or null (replayed y(t_end))
+  double *gy0;            // [n_cells][ns]
+  double *g_cells;        // [n_cells][nr] or null
+  int32_t *status;        // [n_cells] or null
+};
+
 size_t bdf_lds_bytes(const DNet &n);
 int bdf_resident_blocks(const DNet &n);
 hipError_t launch_bdf(const DNet &n, const double *la, int64_t n_cells, double *y, const double *T,
                       const BdfParams &P, const CellOut &out, const TapeView &tv, const WsView &W,
                       unsigned *queue, int grid, hipStream_t st);
+hipError_t launch_reset_queue(unsigned *queue, hipStream_t st);
+hipError_t launch_adjoint(const DNet &n, const double *la, int64_t n_cells, const AdjIO &io,
+                          const BdfParams &P, const WsView &W, const AdjView &A, unsigned *queue,
+                          int grid, hipStream_t st);
+hipError_t launch_sum_rows(const double *part, int64_t rows, int nr, double *out, hipStream_t st);
 hipError_t launch_lu_factor(int n, int lda, int64_t nmat, double *A, int *piv, int *info,
                             hipStream_t st);
 hipError_t launch_lu_solve(int n, int lda, int64_t nmat, const double *LU, const int *piv,

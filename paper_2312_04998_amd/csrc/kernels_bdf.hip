@@ -22,204 +22,9 @@
 //     safety * err^(-1/(q+1)) in [0.2, 10], safety = 0.9*9/(8 + iterations)
 //   order change after q+1 equal steps, to the best of q-1, q, q+1
 //   M refactored whenever c changes; J refreshed only on Newton failure.
-#include "devchem.h"
-#include "devla.h"
-#include "devbdf.h"
+#include "devstep.h"
 
 namespace ac {
-
-constexpr int QMAX = 5, NDROW = QMAX + 3, NEWTON_MAXITER = 4;
-constexpr double MIN_FACTOR = 0.2, MAX_FACTOR = 10.0;
-
-// gamma_q = sum_{m=1..q} 1/m (summed in increasing m), alpha_q = gamma_q,
-// error constant 1/(q+1)
-__device__ __forceinline__ double bdf_gamma(int q) {
-  double g = 0.0;
-  for (int m = 1; m <= q; ++m) g += 1.0 / m;
-  return g;
-}
-__device__ __forceinline__ double bdf_errc(int q) { return 1.0 / (q + 1); }
-
-__device__ __forceinline__ double pow_neg(double x, double e) {
-  return x == 0.0 ? INFINITY : pow(x, -e);
-}
-
-// One LDS region serves, at different times, the RHS rate block and its
-// partial-sum slots, the LU panel, and the solves' diagonal block.
-__host__ __device__ inline int bdf_scratch_doubles(const DNet &n) {
-  const int rhs = n.nr + (n.rhs.n_slot > 0 ? n.rhs.n_slot : 1);
-  const int la = la_scratch_doubles(n.ns);
-  return rhs > la ? rhs : la;
-}
-
-// Per-workgroup view of one cell's work.
-struct CellCtx {
-  const DNet *n;
-  double *kg;      // rate coefficients (slot, global)
-  double *Jg;      // Jacobian values (slot, global)
-  double *tailp;   // Jacobian tail partials (slot, global)
-  double *M;       // Newton matrix / LU (slot, global)
-  int *piv;        // pivots (slot, global)
-  int *perm;       // row permutation of the factorisation (slot, global)
-  double *D;       // difference array [NDROW][ns] (slot, global)
-  int lda;
-  double *rs, *part, *scr, *tmp, *red;   // LDS: rate block + slots | LU panel | solve block
-  int *redi, *ipiv;
-  int cnt[ST_N];   // per-cell counters (identical on every thread)
-};
-
-template <int NT>
-__device__ __forceinline__ double wg_rms(const double *x, double mul, const double *scale, int n,
-                                         double *red) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += NT) {
-    const double v = mul * x[i] / scale[i];
-    s += v * v;
-  }
-  return sqrt(wg_sum<NT>(s, red) / n);
-}
-
-template <int NT>
-__device__ __forceinline__ bool wg_any(bool b, double *red) {
-  return wg_sum<NT>(b ? 1.0 : 0.0, red) > 0.0;
-}
-
-// f = S R(y) with the cell's coefficients; y and f in LDS.
-template <int NT>
-__device__ __forceinline__ void cell_rhs(CellCtx &cx, const double *y, double *f) {
-  const DNet &n = *cx.n;
-  constexpr int U = 4;
-  for (int j0 = threadIdx.x; j0 < n.nr; j0 += U * NT) {
-    uint32_t pr[U];
-    double kv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = j0 + u * NT;
-      pr[u] = j < n.nr ? n.rpair[j] : 0u;
-      kv[u] = j < n.nr ? cx.kg[j] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = j0 + u * NT;
-      if (j < n.nr) cx.rs[j] = reaction_rate(pr[u], kv[u], y);
-    }
-  }
-  __syncthreads();
-  segsum_chunks<NT, LAYOUT_SELL, false, false>(n.rhs, cx.rs, y, cx.part, f);
-  __syncthreads();
-  segsum_finish<NT, false>(n.rhs, cx.part, f);
-  __syncthreads();
-  cx.cnt[ST_RHS]++;
-}
-
-// Jacobian values on the pattern at y (LDS) into the slot.
-template <int NT>
-__device__ __forceinline__ void cell_jac(CellCtx &cx, const double *y) {
-  const DNet &n = *cx.n;
-  segsum_chunks<NT, LAYOUT_SELL, true, false>(n.jtail, cx.kg, y, cx.tailp, nullptr);
-  __syncthreads();
-  constexpr int EU = 4;
-  for (int e0 = threadIdx.x; e0 < n.nnz_j; e0 += EU * NT) {
-    uint32_t h0[EU], h1[EU], td[EU];
-#pragma unroll
-    for (int u = 0; u < EU; ++u) {
-      const int e = e0 + u * NT;
-      const bool ok = e < n.nnz_j;
-      h0[u] = ok ? n.jhead0[e] : 2047u << 16;
-      h1[u] = ok ? n.jhead1[e] : 2047u << 16;
-      td[u] = ok ? n.jtaildesc[e] : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < EU; ++u) {
-      const int e = e0 + u * NT;
-      if (e < n.nnz_j) {
-        double acc = term(h0[u], cx.kg, y);
-        acc = __dadd_rn(acc, term(h1[u], cx.kg, y));
-        const int q0 = int(td[u] >> 8), nq = int(td[u] & 255u);
-        for (int q = 0; q < nq; ++q) acc = __dadd_rn(acc, cx.tailp[q0 + q]);
-        cx.Jg[e] = acc;
-      }
-    }
-  }
-  __syncthreads();
-  cx.cnt[ST_JAC]++;
-}
-
-// M = I - c J (dense, row-major, lda) from the pattern values, then LU.
-template <int NT>
-__device__ __forceinline__ void cell_factor(CellCtx &cx, double c) {
-  const DNet &n = *cx.n;
-  const int ns = n.ns, lda = cx.lda;
-  for (int e = threadIdx.x; e < ns * lda; e += NT) {
-    const int i = e / lda, a = e - i * lda;
-    cx.M[e] = (i == a) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  constexpr int EU = 4;
-  for (int e0 = threadIdx.x; e0 < n.nnz_j; e0 += EU * NT) {
-    int ri[EU], ci[EU];
-    double jv[EU];
-#pragma unroll
-    for (int u = 0; u < EU; ++u) {
-      const int e = e0 + u * NT;
-      const bool ok = e < n.nnz_j;
-      ri[u] = ok ? n.jent_row[e] : 0;
-      ci[u] = ok ? n.jent_col[e] : 0;
-      jv[u] = ok ? cx.Jg[e] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < EU; ++u)
-      if (e0 + u * NT < n.nnz_j)
-        cx.M[size_t(ri[u]) * lda + ci[u]] = (ri[u] == ci[u] ? 1.0 : 0.0) - c * jv[u];
-  }
-  __syncthreads();
-  wg_lu<NT>(cx.M, lda, ns, cx.piv, cx.perm, cx.scr, cx.red, cx.redi, cx.ipiv);
-  cx.cnt[ST_LU]++;
-}
-
-// Resample D[0..q] for a step change by `factor` (Shampine & Reichelt
-// 1997): D <- (R(factor) U)^T D with U = R(1).
-template <int NT>
-__device__ __forceinline__ void rescale_diffs(CellCtx &cx, int q, double factor, int ns) {
-  constexpr int W = QMAX + 1;
-  double *RU = cx.red + 16, *R = RU + W * W, *U = R + W * W;   // LDS
-  if (threadIdx.x == 0) {
-    for (int j = 0; j <= q; ++j) {
-      R[j] = 1.0;
-      U[j] = 1.0;
-    }
-    for (int i = 1; i <= q; ++i) {
-      R[i * W] = 0.0;
-      U[i * W] = 0.0;
-      for (int j = 1; j <= q; ++j) {
-        R[i * W + j] = R[(i - 1) * W + j] * ((i - 1 - factor * j) / i);
-        U[i * W + j] = U[(i - 1) * W + j] * ((i - 1 - 1.0 * j) / i);
-      }
-    }
-    for (int i = 0; i <= q; ++i)
-      for (int j = 0; j <= q; ++j) {
-        double s = 0.0;
-        for (int m = 0; m <= q; ++m) s += R[i * W + m] * U[m * W + j];
-        RU[i * W + j] = s;
-      }
-  }
-  __syncthreads();
-  for (int x = threadIdx.x; x < ns; x += NT) {
-    double old[QMAX + 1];
-#pragma unroll
-    for (int i = 0; i <= QMAX; ++i) old[i] = i <= q ? cx.D[size_t(i) * ns + x] : 0.0;
-#pragma unroll
-    for (int kk = 0; kk <= QMAX; ++kk) {
-      if (kk > q) break;
-      double s = 0.0;
-#pragma unroll
-      for (int i = 0; i <= QMAX; ++i)
-        if (i <= q) s += RU[i * W + kk] * old[i];
-      cx.D[size_t(kk) * ns + x] = s;
-    }
-  }
-  __syncthreads();
-}
 
 __device__ __forceinline__ void tape_put(const TapeView &tv, int64_t cell, int &len, int type,
                                          int q, double val) {
@@ -571,6 +376,12 @@ hipError_t launch_bdf(const DNet &n, const double *la, int64_t n_cells, double *
   const int g = int(n_cells < grid ? n_cells : grid);
   hipLaunchKernelGGL(k_bdf<BDF_NT>, dim3(g), dim3(BDF_NT), lds, st, n, la, n_cells, y, T, P, out,
                      tv, W, queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_queue(unsigned *queue, hipStream_t st) {
+  if (!queue) return hipSuccess;
+  hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, queue);
   return hipGetLastError();
 }
 

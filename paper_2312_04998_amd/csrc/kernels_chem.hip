@@ -306,6 +306,17 @@ static hipError_t vjp_nt(const DNet &n, const double *la, int64_t n_cells, const
   return hipGetLastError();
 }
 
+hipError_t launch_sum_rows(const double *part, int64_t rows, int nr, double *out, hipStream_t st) {
+  if (rows == 0) {
+    hipLaunchKernelGGL(k_fill, dim3((nr + RED_NT - 1) / RED_NT), dim3(RED_NT), 0, st, out,
+                       int64_t(nr), 0.0);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_sum_rows, dim3((nr + RED_NT - 1) / RED_NT), dim3(RED_NT), 0, st, part,
+                     int(rows), nr, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_vjp(const DNet &n, const double *la, int64_t n_cells, const double *y,
                       const double *T, const double *v, double *gy, double *g_logalpha,
                       double *part, int part_rows, hipStream_t st) {
