@@ -281,6 +281,9 @@ ac_status ac_integrate_plain(ac_ws *ws, const double *log_alpha, int64_t n_cells
  *   cell_status [n_cells] DEVICE or NULL: AC_CELL_OK, AC_CELL_BADINPUT
  *     (dL_dy0 = lambda, no parameter terms) or AC_CELL_TAPE (tape_len < 0,
  *     > tape_cap, or an order outside 1..5; dL_dy0 = lambda).
+ *   cell_stats [n_cells][AC_NSTAT] DEVICE or NULL: steps reversed, Newton
+ *     iterations of the replays, Jacobians, factorisations and RHS
+ *     evaluations (the rejection and order fields are 0).
  * Only rtol and atol of opts are used (they scale the replay's convergence
  * test). The workspace grows its checkpoint store on the first call with a
  * larger tape_cap (a device allocation, after synchronising the stream);
@@ -292,7 +295,7 @@ ac_status ac_integrate_adjoint(ac_ws *ws, const double *log_alpha, int64_t n_cel
                                const ac_event *tape, int32_t tape_cap, const int32_t *tape_len,
                                const double *lambda, double *y_final, double *dL_dy0,
                                double *g_cells, double *dL_dlogalpha, int32_t *cell_status,
-                               ac_stream stream);
+                               int32_t *cell_stats, ac_stream stream);
 
 /* Status text and the calling thread's last error message (incl. HIP's). */
 const char *ac_status_string(ac_status s);

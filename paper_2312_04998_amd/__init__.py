@@ -79,7 +79,7 @@ def _load() -> C.CDLL:
         "ac_integrate": [vp, vp, i64, vp, vp, d, vp, vp, vp, vp, i32, vp, vp],
         "ac_integrate_plain": [vp, vp, i64, vp, vp, d, vp, vp, vp, vp],
         "ac_integrate_adjoint": [vp, vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
-                                 vp],
+                                 vp, vp],
     }
     for name, args in sig2.items():
         f = getattr(L, name)
@@ -390,7 +390,9 @@ class Workspace:
                 want_glog=True, want_cells=False, want_y=False, stream=None):
         """Discrete adjoint (ac_integrate_adjoint) of L = sum <lam, y(t_end)>
         over the recorded tape of an earlier integrate(..., tape_cap=...).
-        Returns dict of device tensors: dL_dy0 [n, ns], status [n] and, as
+        Returns dict of device tensors: dL_dy0 [n, ns], status [n], stats
+        [n, NSTAT] (steps reversed, replay Newton iterations, Jacobians,
+        factorisations, RHS evaluations) and, as
         requested, dL_dlogalpha [nr] (summed over cells in cell order),
         g_cells [n, nr] and the replayed y_final [n, ns]."""
         import torch
@@ -407,7 +409,8 @@ class Workspace:
         dev = y0.device
         gy0 = torch.empty_like(y0)
         status = torch.empty(n, dtype=torch.int32, device=dev)
-        out = {"dL_dy0": gy0, "status": status}
+        stats = torch.empty((n, NSTAT), dtype=torch.int32, device=dev)
+        out = {"dL_dy0": gy0, "status": status, "stats": stats}
         g_cells = glog = yf = None
         if want_glog or want_cells:
             g_cells = torch.empty((n, nr), dtype=torch.float64, device=dev)
@@ -423,7 +426,7 @@ class Workspace:
         check(lib.ac_integrate_adjoint(self.handle, _ptr(log_alpha), n, _ptr(y0), _ptr(T),
                                        C.byref(o), _ptr(tape), int(tape.shape[1]),
                                        _ptr(tape_len), _ptr(lam), _ptr(yf), _ptr(gy0),
-                                       _ptr(g_cells), _ptr(glog), _ptr(status),
+                                       _ptr(g_cells), _ptr(glog), _ptr(status), _ptr(stats),
                                        _stream(stream)), "ac_integrate_adjoint")
         return out
 

@@ -600,7 +600,7 @@ ac_status ac_integrate_adjoint(ac_ws *ws, const double *log_alpha, int64_t n_cel
                                const ac_event *tape, int32_t tape_cap, const int32_t *tape_len,
                                const double *lambda, double *y_final, double *dL_dy0,
                                double *g_cells, double *dL_dlogalpha, int32_t *cell_status,
-                               ac_stream stream) {
+                               int32_t *cell_stats, ac_stream stream) {
   if (ac_status s = integ_args(ws, n_cells, y0, T, 0.0, opts)) return s;
   if (tape_cap <= 0) return fail(AC_EINVAL, "tape_cap must be > 0");
   if (n_cells && (!tape || !tape_len || !lambda || !dL_dy0))
@@ -612,7 +612,7 @@ ac_status ac_integrate_adjoint(ac_ws *ws, const double *log_alpha, int64_t n_cel
     if (ac_status s = adj_reserve(ws, tape_cap, st)) return s;
     ac::BdfParams P{opts->rtol, opts->atol, opts->h0, 0.0, opts->q_max, opts->max_steps};
     ac::AdjIO io{reinterpret_cast<const ac::AcEvent *>(tape), tape_len, tape_cap, y0, T, lambda,
-                 y_final, dL_dy0, g_cells, cell_status};
+                 y_final, dL_dy0, g_cells, cell_status, cell_stats};
     hipError_t e = ac::launch_adjoint(ws->net->d, log_alpha, n_cells, io, P, ws->W, ws->A,
                                       ws->queue, ws->n_slots, st);
     if (e != hipSuccess) return hip_fail(e, "ac_integrate_adjoint launch");

@@ -65,6 +65,7 @@ struct AdjIO {
   double *gy0;            // [n_cells][ns]
   double *g_cells;        // [n_cells][nr] or null
   int32_t *status;        // [n_cells] or null
+  int32_t *stats;         // [n_cells][ST_N] or null
 };
 
 size_t bdf_lds_bytes(const DNet &n);

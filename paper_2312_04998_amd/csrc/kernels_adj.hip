@@ -19,7 +19,9 @@
 //
 // One persistent workgroup handles one cell at a time (device queue). It
 // replays the tape forward once with converged correctors, keeping the
-// difference array every CK_EVERY accepted steps; the reverse sweep then
+// difference array every CK_EVERY accepted steps (the replay of a segment
+// depends only on its checkpoint, so a recomputed segment repeats the first
+// pass bit for bit); the reverse sweep then
 // walks the segments backwards, recomputing each segment forward from its
 // checkpoint (storing the converged y of every step) before reversing it.
 // Each reverse step refactors M at the converged y and does one transposed
@@ -35,28 +37,39 @@ struct AdjVecs {
   double *f, *yn, *dd, *psi, *scl, *yp, *dy;
 };
 
-// Converged corrector for a recorded step (q, h): Newton on G(d) = 0 with
-// the matrix refreshed at the current iterate whenever the contraction is
-// slow, until the update is at rounding level; then D advances. Leaves the
-// converged y in v.yn. Same rules as the oracle's replay.
+// Converged corrector for a recorded step (q, h): Newton on G(d) = 0 until
+// the update is at rounding level, then D advances. The Newton matrix
+// carries over from the previous step (refactored with the same Jacobian
+// when c changes, as the integrator does) and J is refreshed at the
+// current iterate whenever the contraction is slow; cM is the c of the
+// factored matrix, 0 when there is none (J is then formed at y_pred).
+// Every checkpointed segment starts from cM = 0, so a segment's replay
+// depends only on its checkpoint and is bitwise repeatable. The converged
+// y is left in v.yn. Stopping rules are the oracle's replay rules.
 template <int NT>
 __device__ __forceinline__ void replay_step(CellCtx &cx, const AdjVecs &v, int q, double h,
-                                            double rtol, double atol, int ns) {
+                                            double rtol, double atol, int ns, double &cM) {
   predict<NT>(cx, q, rtol, atol, ns, v.yp, v.scl, v.psi);
   const double c = h / bdf_gamma(q);
   for (int x = threadIdx.x; x < ns; x += NT) v.dd[x] = 0.0;
   __syncthreads();
+  if (cM == 0.0) cell_jac<NT>(cx, v.yp);
+  if (cM != c) {
+    cell_factor<NT>(cx, c);
+    cM = c;
+  }
   double prev = INFINITY;
-  bool fresh = false;
+  bool refresh = false;
   for (int it = 0; it < 60; ++it) {
     for (int x = threadIdx.x; x < ns; x += NT) v.yn[x] = v.yp[x] + v.dd[x];
     __syncthreads();
-    if (!fresh) {
+    if (refresh) {
       cell_jac<NT>(cx, v.yn);
       cell_factor<NT>(cx, c);
-      fresh = true;
+      refresh = false;
     }
     cell_rhs<NT>(cx, v.yn, v.f);
+    cx.cnt[ST_NEWTON]++;
     for (int x = threadIdx.x; x < ns; x += NT) v.dy[x] = -(v.dd[x] - c * v.f[x] + v.psi[x]);
     __syncthreads();
     wg_solve<NT>(cx.M, cx.lda, ns, cx.perm, v.dy, cx.tmp, false, cx.scr);
@@ -65,7 +78,7 @@ __device__ __forceinline__ void replay_step(CellCtx &cx, const AdjVecs &v, int q
     __syncthreads();
     if (dn <= 1e-10) break;                       // converged
     if (dn <= 1e-7 && dn > 0.5 * prev) break;     // at rounding level
-    if (dn > 0.1 * prev) fresh = false;           // slow: full Newton
+    if (dn > 0.1 * prev) refresh = true;          // slow: Jacobian at the iterate
     prev = dn;
   }
   for (int x = threadIdx.x; x < ns; x += NT) v.yn[x] = v.yp[x] + v.dd[x];
@@ -241,6 +254,7 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
       __syncthreads();
       // forward replay with checkpoints every CK_EVERY accepted steps
       int nck = 0, nstep = 0;   // nck <= cap / CK_EVERY + 1 = A.ckcap since nstep <= nev <= cap
+      double cM = 0.0;
       for (int e = 0; e < nev; ++e) {
         const AcEvent E = ev[e];
         if (E.type == EV_STEP) {
@@ -249,8 +263,9 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
             for (size_t i = threadIdx.x; i < dsz; i += NT) dst[i] = cx.D[i];
             if (threadIdx.x == 0) ckev[nck] = e;
             ++nck;
+            cM = 0.0;
           }
-          replay_step<NT>(cx, v, E.q, E.val, P.rtol, P.atol, ns);
+          replay_step<NT>(cx, v, E.q, E.val, P.rtol, P.atol, ns, cM);
           ++nstep;
         } else if (E.type == EV_RESCALE) {
           rescale_diffs<NT>(cx, E.q, E.val, ns);
@@ -273,10 +288,11 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
         __syncthreads();
         const int e0 = ckev[s];
         int i = 0;
+        double cM = 0.0;
         for (int e = e0; e < e_end; ++e) {
           const AcEvent E = ev[e];
           if (E.type == EV_STEP) {
-            replay_step<NT>(cx, v, E.q, E.val, P.rtol, P.atol, ns);
+            replay_step<NT>(cx, v, E.q, E.val, P.rtol, P.atol, ns, cM);
             for (int x = threadIdx.x; x < ns; x += NT) segY[size_t(i) * ns + x] = yn[x];
             ++i;
           } else if (E.type == EV_RESCALE) {
@@ -291,6 +307,7 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
             for (int x = threadIdx.x; x < ns; x += NT) yn[x] = segY[size_t(i) * ns + x];
             __syncthreads();
             reverse_step<NT>(cx, v, Db, E.q, E.val, ns, grow);
+            cx.cnt[ST_STEPS]++;
           } else if (E.type == EV_RESCALE) {
             apply_resample<NT, true>(resample_matrix<NT>(cx, E.q, E.val), Db, E.q, ns);
           }
@@ -322,6 +339,10 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
     }
     for (int x = threadIdx.x; x < ns; x += NT) io.gy0[cell * ns + x] = Db[x];
     if (threadIdx.x == 0 && io.status) io.status[cell] = status;
+    if (threadIdx.x == 0 && io.stats) {
+      int *st = io.stats + cell * ST_N;
+      for (int i = 0; i < ST_N; ++i) st[i] = cx.cnt[i];
+    }
     __syncthreads();
   }
 }
