@@ -48,6 +48,9 @@ def parse():
     p.add_argument("--plain-cells", type=int, default=2, help="cells timed through the plain loop")
     p.add_argument("--adj-cells", type=int, default=256)
     p.add_argument("--adj-max-steps", type=int, default=1500)
+    p.add_argument("--copy-probe", action="store_true",
+                   help="also run a plain device copy of the densities (known bytes) so HBM "
+                        "counters can be calibrated in the same profile")
     return p.parse_args()
 
 
@@ -227,6 +230,14 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall * 1e3 / args.steps
+
+    if args.copy_probe:
+        # a copy of known size: reads and writes C * ns * 8 bytes once each
+        ycopy = torch.empty_like(y)
+        for _ in range(3):
+            ycopy.copy_(y)
+        torch.cuda.synchronize()
+        del ycopy
 
     # the other chemistry kernels of the path, timed the same way
     for _ in range(2):

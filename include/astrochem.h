@@ -67,8 +67,12 @@ typedef enum {
   AC_LAYOUT_SELL = 1,  /* sliced ELLPACK over row chunks: slices of sell_c chunks,
                           nonzero k of every chunk of a slice stored together, chunks
                           sorted by length within windows of sell_sigma (SELL-C-sigma) */
-  AC_LAYOUT_COO = 2    /* coordinate triplets, scattered with LDS atomics
+  AC_LAYOUT_COO = 2,   /* coordinate triplets, scattered with LDS atomics
                           (summation order not reproducible run to run) */
+  AC_LAYOUT_RUNS = 3   /* CRS nonzeros cut into equal runs of 32 per lane
+                          whatever the row lengths (merge-style partition); a
+                          32-bit mask per run marks row starts, each row adds
+                          its run partials in order */
 } ac_layout;
 
 /* Order in which species rows are traversed (Sec. 3 reorders rows by their

@@ -2,6 +2,8 @@
 // term evaluation, chunked gather sums over a schedule, reaction records.
 #pragma once
 
+#include <climits>
+
 #include "devnet.h"
 
 namespace ac {
@@ -38,29 +40,54 @@ __device__ __forceinline__ void segsum_chunks(const DSched &s, const double *__r
                                               const double *__restrict__ ys, double *part,
                                               double *__restrict__ out) {
   if (LAYOUT == LAYOUT_SELL) {
+    // SELL_P positions per lane at once, their descriptors, destinations
+    // and items requested before any is used; a wave's 64 lanes share one
+    // slice per position, so widths are wave-uniform. One position per
+    // round measured fastest (more cost occupancy through registers).
+    constexpr int SELL_P = 1;
     const int npos = s.n_slice * SELL_C;
-    for (int pos = threadIdx.x; pos < npos; pos += NT) {
-      const int ch = IDENT ? (pos < s.n_chunk ? pos : -1) : s.sell_chunk[pos];
-      const int sl = pos / SELL_C;
-      const int base = s.slice_ptr[sl];
-      const int width = (s.slice_ptr[sl + 1] - base) / SELL_C;
-      const int len = s.sell_len[pos];
-      const uint32_t *it = s.sell_items + base + (pos - sl * SELL_C);
-      double acc = 0.0;
-      for (int k0 = 0; k0 < width; k0 += UNROLL) {
-        uint32_t v[UNROLL];
+    for (int pos0 = threadIdx.x; pos0 < npos; pos0 += SELL_P * NT) {
+      int width[SELL_P], len[SELL_P], dst[SELL_P];
+      const uint32_t *it[SELL_P];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) v[u] = (k0 + u < width) ? it[(k0 + u) * SELL_C] : PAD_ITEM;
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-          const double t = term(v[u], A, ys);
-          if (k0 + u < len) acc = __dadd_rn(acc, t);
-        }
+      for (int p = 0; p < SELL_P; ++p) {
+        const int pos = pos0 + p * NT;
+        const bool ok = pos < npos;
+        const int sl = ok ? pos / SELL_C : 0;
+        const int base = ok ? s.slice_ptr[sl] : 0;
+        width[p] = ok ? (s.slice_ptr[sl + 1] - base) / SELL_C : 0;
+        len[p] = ok ? s.sell_len[pos] : 0;
+        const int ch = !ok ? -1 : (IDENT ? (pos < s.n_chunk ? pos : -1) : s.sell_chunk[pos]);
+        dst[p] = ch >= 0 ? s.chunk_dst[ch] : INT_MIN;
+        it[p] = s.sell_items + base + (ok ? pos - sl * SELL_C : 0);
       }
-      if (ch >= 0) {
-        const int d = s.chunk_dst[ch];
-        if (d >= 0) put<STREAM>(out + d, acc);
-        else part[-1 - d] = acc;
+      int wmax = 0;
+#pragma unroll
+      for (int p = 0; p < SELL_P; ++p) wmax = width[p] > wmax ? width[p] : wmax;
+      double acc[SELL_P];
+#pragma unroll
+      for (int p = 0; p < SELL_P; ++p) acc[p] = 0.0;
+      for (int k0 = 0; k0 < wmax; k0 += UNROLL) {
+        uint32_t v[SELL_P][UNROLL];
+#pragma unroll
+        for (int p = 0; p < SELL_P; ++p)
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u)
+            v[p][u] = (k0 + u < width[p]) ? it[p][(k0 + u) * SELL_C] : PAD_ITEM;
+#pragma unroll
+        for (int p = 0; p < SELL_P; ++p)
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u) {
+            const double t = term(v[p][u], A, ys);
+            if (k0 + u < len[p]) acc[p] = __dadd_rn(acc[p], t);
+          }
+      }
+#pragma unroll
+      for (int p = 0; p < SELL_P; ++p) {
+        const int d = dst[p];
+        if (d == INT_MIN) continue;
+        if (d >= 0) put<STREAM>(out + d, acc[p]);
+        else part[-1 - d] = acc[p];
       }
     }
   } else {
@@ -81,6 +108,50 @@ __device__ __forceinline__ void segsum_chunks(const DSched &s, const double *__r
       if (d >= 0) put<STREAM>(out + d, acc);
       else part[-1 - d] = acc;
     }
+  }
+}
+
+// Equal-run partials: lane t sums the RUN_ITEMS items of run t left to
+// right, closing a partial (into part, numbered from run_slot[t]) wherever
+// the run's mask marks a new segment. All of a run's items are requested
+// with four 16-byte loads before any is used.
+template <int NT>
+__device__ __forceinline__ void runsum_partials(const DSched &s, const double *__restrict__ A,
+                                                const double *__restrict__ ys, double *part) {
+  for (int t = threadIdx.x; t < s.n_run; t += NT) {
+    const uint32_t mask = s.run_mask[t];
+    int slot = s.run_slot[t];
+    const int len = s.n_item - t * RUN_ITEMS < RUN_ITEMS ? s.n_item - t * RUN_ITEMS : RUN_ITEMS;
+    const uint4 *it4 = reinterpret_cast<const uint4 *>(s.items + size_t(t) * RUN_ITEMS);
+    uint4 w[RUN_ITEMS / 4];
+#pragma unroll
+    for (int q = 0; q < RUN_ITEMS / 4; ++q) w[q] = it4[q];
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < RUN_ITEMS; ++k) {
+      const uint4 &wq = w[k >> 2];
+      const uint32_t it = (k & 3) == 0 ? wq.x : (k & 3) == 1 ? wq.y : (k & 3) == 2 ? wq.z : wq.w;
+      if (k < len) {
+        if (k > 0 && ((mask >> k) & 1u)) {
+          part[slot++] = acc;
+          acc = 0.0;
+        }
+        acc = __dadd_rn(acc, term(it, A, ys));
+      }
+    }
+    if (len > 0) part[slot] = acc;
+  }
+}
+
+// out[seg_out[k]] = sum of segment k's run partials, in order.
+template <int NT, bool STREAM>
+__device__ __forceinline__ void runsum_finish(const DSched &s, const double *part,
+                                              double *__restrict__ out) {
+  for (int k = threadIdx.x; k < s.n_seg; k += NT) {
+    const int q0 = s.seg_run[2 * k], nq = s.seg_run[2 * k + 1];
+    double acc = 0.0;
+    for (int q = 0; q < nq; ++q) acc = __dadd_rn(acc, part[q0 + q]);
+    put<STREAM>(out + s.seg_out[k], acc);
   }
 }
 
@@ -107,6 +178,12 @@ __device__ __forceinline__ void segsum(const DSched &s, const double *A, const d
       atomicAdd(&part[s.coo_out[p]], term(s.items[p], A, ys));
     __syncthreads();
     for (int i = threadIdx.x; i < s.n_seg; i += NT) out[i] = part[i];
+    return;
+  }
+  if (LAYOUT == LAYOUT_RUNS) {
+    runsum_partials<NT>(s, A, ys, part);
+    __syncthreads();
+    runsum_finish<NT, false>(s, part, out);
     return;
   }
   segsum_chunks<NT, LAYOUT, false, false>(s, A, ys, part, out);

@@ -7,7 +7,8 @@
 
 namespace ac {
 
-constexpr int LAYOUT_CSR = 0, LAYOUT_SELL = 1, LAYOUT_COO = 2;
+constexpr int LAYOUT_CSR = 0, LAYOUT_SELL = 1, LAYOUT_COO = 2, LAYOUT_RUNS = 3;
+constexpr int RUN_ITEMS = 32;   // items per run of the equal-run partition
 
 struct DSched {
   int n_seg, n_chunk, n_item, n_slot, n_multi;
@@ -17,6 +18,9 @@ struct DSched {
   const int32_t *slice_ptr, *sell_chunk, *sell_len;
   const uint32_t *sell_items;
   const int32_t *coo_out;
+  int n_run, n_rslot;
+  const uint32_t *run_mask;
+  const int32_t *run_slot, *seg_run;
 };
 
 struct DNet {

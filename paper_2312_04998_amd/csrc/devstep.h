@@ -100,7 +100,7 @@ __device__ __forceinline__ void cell_rhs(CellCtx &cx, const double *y, double *f
 template <int NT>
 __device__ __forceinline__ void cell_jac(CellCtx &cx, const double *y) {
   const DNet &n = *cx.n;
-  segsum_chunks<NT, LAYOUT_SELL, true, false>(n.jtail, cx.kg, y, cx.tailp, nullptr);
+  runsum_partials<NT>(n.jtail, cx.kg, y, cx.tailp);
   __syncthreads();
   constexpr int EU = 4;
   for (int e0 = threadIdx.x; e0 < n.nnz_j; e0 += EU * NT) {

@@ -126,7 +126,7 @@ __device__ __forceinline__ void cell_vjp(CellCtx &cx, const double *y, const dou
     }
   }
   __syncthreads();
-  segsum_chunks<NT, LAYOUT_SELL, true, false>(n.gy, kw, y, part, u);
+  segsum_chunks<NT, LAYOUT_SELL, false, false>(n.gy, kw, y, part, u);
   __syncthreads();
   segsum_finish<NT, false>(n.gy, part, u);
   __syncthreads();

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(NT) void k_jac(DNet n, const double *__restrict__ l
     cell_temperature(T[c], L, invT);
     for_reactions<NT>(n, la_over, L, invT, [&](int j, double kj, uint32_t) { ks[j] = kj; });
     __syncthreads();
-    segsum_chunks<NT, LAYOUT_SELL, true, false>(n.jtail, ks, ys, part, nullptr);
+    runsum_partials<NT>(n.jtail, ks, ys, part);
     __syncthreads();
     double *out = jvals + c * n.nnz_j;
     constexpr int EU = 4;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(NT) void k_vjp(DNet n, const double *__restrict__ l
     __syncthreads();
     if (gy) {
       double *out = gy + c * ns;
-      segsum_chunks<NT, LAYOUT_SELL, true, false>(n.gy, kw, ys, part, out);
+      segsum_chunks<NT, LAYOUT_SELL, false, false>(n.gy, kw, ys, part, out);
       __syncthreads();
       segsum_finish<NT, false>(n.gy, part, out);
     }
@@ -215,7 +215,9 @@ static int grid_for(K kernel, int nt, size_t lds, int64_t n_cells) {
 }
 
 size_t rhs_lds_bytes(const DNet &n) {
-  const int extra = n.layout == LAYOUT_COO ? n.ns : n.rhs.n_slot;
+  const int extra = n.layout == LAYOUT_COO    ? n.ns
+                    : n.layout == LAYOUT_RUNS ? n.rhs.n_rslot
+                                              : n.rhs.n_slot;
   return sizeof(double) * size_t(n.ns + n.nr + (extra > 0 ? extra : 1));
 }
 
@@ -254,10 +256,12 @@ static hipError_t rhs_nt(const DNet &n, const double *la, int64_t n_cells, const
                          const double *T, const double *k, double *dydt, hipStream_t st) {
   if (k) {
     if (n.layout == LAYOUT_SELL) return rhs_variant<NT, LAYOUT_SELL, true>(n, la, n_cells, y, T, k, dydt, st);
+    if (n.layout == LAYOUT_RUNS) return rhs_variant<NT, LAYOUT_RUNS, true>(n, la, n_cells, y, T, k, dydt, st);
     if (n.layout == LAYOUT_COO) return rhs_variant<NT, LAYOUT_COO, true>(n, la, n_cells, y, T, k, dydt, st);
     return rhs_variant<NT, LAYOUT_CSR, true>(n, la, n_cells, y, T, k, dydt, st);
   }
   if (n.layout == LAYOUT_SELL) return rhs_variant<NT, LAYOUT_SELL, false>(n, la, n_cells, y, T, k, dydt, st);
+  if (n.layout == LAYOUT_RUNS) return rhs_variant<NT, LAYOUT_RUNS, false>(n, la, n_cells, y, T, k, dydt, st);
   if (n.layout == LAYOUT_COO) return rhs_variant<NT, LAYOUT_COO, false>(n, la, n_cells, y, T, k, dydt, st);
   return rhs_variant<NT, LAYOUT_CSR, false>(n, la, n_cells, y, T, k, dydt, st);
 }

@@ -139,6 +139,36 @@ void build_schedule(const std::vector<std::vector<uint32_t>> &seg_items,
   s.n_chunk = int(s.chunk_ptr.size() - 1);
   s.n_item = int(s.items.size());
 
+  // equal runs of RUN_LEN items over the whole list (merge-style partition:
+  // every lane gets the same amount of work whatever the segment lengths)
+  s.n_run = (s.n_item + RUN_LEN - 1) / RUN_LEN;
+  s.run_mask.assign(s.n_run, 0u);
+  s.run_slot.assign(s.n_run, 0);
+  s.seg_run.assign(size_t(2) * s.n_seg, 0);
+  {
+    std::vector<int32_t> seg_of(s.n_item);
+    for (int k = 0; k < s.n_seg; ++k)
+      for (int q = s.chunk_ptr[s.seg_chunk[k]]; q < s.chunk_ptr[s.seg_chunk[k + 1]]; ++q) seg_of[q] = k;
+    int slot = 0;
+    for (int t = 0; t < s.n_run; ++t) {
+      s.run_slot[t] = slot;
+      for (int k = 0; k < RUN_LEN; ++k) {
+        const int i = t * RUN_LEN + k;
+        if (i >= s.n_item) break;
+        if (k == 0 || seg_of[i] != seg_of[i - 1]) {
+          s.run_mask[t] |= 1u << k;
+          const int g = seg_of[i];
+          if (s.seg_run[2 * g + 1] == 0) s.seg_run[2 * g] = slot;
+          ++s.seg_run[2 * g + 1];
+          ++slot;
+        }
+      }
+    }
+    s.n_rslot = slot;
+  }
+  const uint32_t pad_item = pack_item(0, -1, 0);
+  s.items.resize(size_t(s.n_run) * RUN_LEN, pad_item);
+
   // SELL-C-sigma: positions are chunk ids sorted by length (descending,
   // stable) inside windows of sigma chunks, grouped into slices of C.
   s.sell_c = sell_c;
@@ -188,7 +218,7 @@ std::string build_network(int ns, int nr, const int32_t *reactants, const int32_
     return "network larger than AC_MAX_SPECIES / AC_MAX_REACTIONS";
   }
   if (!reactants || !products || !alpha || !beta || !gamma) return "null network array";
-  if (layout < 0 || layout > 2) return "unknown layout";
+  if (layout < 0 || layout > 3) return "unknown layout";
   if (ordering < 0 || ordering > 2) return "unknown ordering";
   if (chunk < 0 || sell_c < 0 || sell_sigma < 0) return "negative chunk/sell parameter";
   chunk = chunk ? chunk : 32;
@@ -330,23 +360,21 @@ std::string build_network(int ns, int nr, const int32_t *reactants, const int32_
         tail_order.push_back(int32_t(e));
       }
     }
-    // every tail chunk writes a slot: force "split" handling by building the
-    // schedule over the tails and remapping single-chunk tails to slots too
-    build_schedule(tails, tail_order, chunk, sell_c, 1, H.jtail);
-    int slot = 0;
-    for (int c = 0, k = 0; k < H.jtail.n_seg; ++k) {
+    build_schedule(tails, tail_order, chunk, sell_c, 1 << 30, H.jtail);
+    // tail partials come from equal runs (RUN_LEN terms per lane); an entry
+    // adds its consecutive run partials
+    for (int k = 0; k < H.jtail.n_seg; ++k) {
       const int e = H.jtail.seg_out[k];
-      const int c0 = H.jtail.seg_chunk[k], c1 = H.jtail.seg_chunk[k + 1];
-      if (c1 - c0 > 255) return "Jacobian entry with too many terms";
-      H.jtaildesc[e] = (uint32_t(slot) << 8) | uint32_t(c1 - c0);
-      for (c = c0; c < c1; ++c) H.jtail.chunk_dst[c] = -1 - slot++;
+      const int first = H.jtail.seg_run[2 * k], cnt = H.jtail.seg_run[2 * k + 1];
+      if (cnt > 255 || first >= (1 << 24)) return "Jacobian entry with too many terms";
+      H.jtaildesc[e] = (uint32_t(first) << 8) | uint32_t(cnt);
     }
-    H.jtail.n_slot = slot;
+    H.jtail.n_slot = H.jtail.n_rslot;
     H.jtail.n_multi = 0;
     H.jtail.multi_out.clear();
     H.jtail.multi_slot.assign(1, 0);
   }
-  build_schedule(gyseg, H.perm, chunk, sell_c, 1, H.gy);
+  build_schedule(gyseg, H.perm, chunk, sell_c, 1 << 30, H.gy);
   // packed per-reaction record (see HostNet::rxpack)
   H.rxpack.assign(size_t(nr) * 16, 0u);
   for (int j = 0; j < nr; ++j) {

@@ -41,7 +41,19 @@ struct Schedule {
   std::vector<uint32_t> sell_items;
   // COO: output index of every item (CSR order)
   std::vector<int32_t> coo_out;
+  // Runs: the CSR item list cut into equal runs of RUN_LEN items (items is
+  // padded to a whole number of runs). run_mask bit k marks item k of the
+  // run as the start of a partial sum (a new segment, or the run's first
+  // item); partials are numbered run by run from run_slot[t]; segment s
+  // (traversal order) owns the consecutive partials seg_run[2s] ..
+  // seg_run[2s] + seg_run[2s+1] - 1.
+  int n_run = 0, n_rslot = 0;
+  std::vector<uint32_t> run_mask;
+  std::vector<int32_t> run_slot;   // [n_run]
+  std::vector<int32_t> seg_run;    // [2 n_seg]
 };
+
+constexpr int RUN_LEN = 32;   // items per run (one 32-bit mask word)
 
 struct HostNet {
   int ns = 0, nr = 0;

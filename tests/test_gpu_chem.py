@@ -57,7 +57,7 @@ def test_rates(acm, torch_dev, oracle_mod, medium_net, med_cells):
     _close(k, ref, 2e-13 / REL * np.abs(ref))
 
 
-@pytest.mark.parametrize("layout", ["csr", "sell", "coo"])
+@pytest.mark.parametrize("layout", ["csr", "sell", "coo", "runs"])
 @pytest.mark.parametrize("ordering", ["natural", "nnz", "rcm"])
 def test_rhs(acm, torch_dev, oracle_mod, medium_net, med_cells, layout, ordering):
     torch = torch_dev
@@ -176,7 +176,7 @@ def test_large_network(acm, torch_dev, oracle_mod):
     cells = synthnet.make_cells(net, 70, synthnet.SEED_BASE + 4)
     y, T = cells.y0, cells.T
     v = np.random.default_rng(1).standard_normal(y.shape)
-    for layout in ("csr", "sell"):
+    for layout in ("csr", "sell", "runs"):
         N = acm.Network.from_synth(net, layout=layout, ordering="rcm")
         f = N.rhs(_t(torch, y), _t(torch, T)).cpu().numpy()
         ref, ab = oracle_mod.rhs(net, y, T, with_abs=True)
@@ -197,10 +197,13 @@ def test_edge_cases(acm, torch_dev, oracle_mod):
     N = acm.Network(net.reactants, net.products, net.alpha, net.beta, net.gamma,
                     composition=np.zeros((3, 6), np.int8))
     y = np.array([[2.0, 7.0, 11.0]])
-    f = N.rhs(_t(torch, y), _t(torch, [40.0])).cpu().numpy()
-    # k = exp(ln alpha) is alpha to within an ulp or two
-    np.testing.assert_allclose(f, [[-2 * 3 * 4 + 2 * 5 * 7, 3 * 4 - 5 * 7, 0.0]], rtol=1e-14)
-    assert f[0, 2] == 0.0
+    for layout in ("csr", "sell", "coo", "runs"):
+        M = acm.Network(net.reactants, net.products, net.alpha, net.beta, net.gamma,
+                        composition=np.zeros((3, 6), np.int8), layout=layout)
+        f = M.rhs(_t(torch, y), _t(torch, [40.0])).cpu().numpy()
+        # k = exp(ln alpha) is alpha to within an ulp or two
+        np.testing.assert_allclose(f, [[-2 * 3 * 4 + 2 * 5 * 7, 3 * 4 - 5 * 7, 0.0]], rtol=1e-14)
+        assert f[0, 2] == 0.0
     # zero cells: a no-op
     e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
     N.rhs(e, torch.empty(0, dtype=torch.float64, device="cuda"))

@@ -145,7 +145,7 @@ def test_tiny_network_parity(acm, torch_dev, oracle_mod, tiny, q_max, years):
         T = np.array([10.0, 20.0, 35.0, 60.0, 150.0, 300.0])
     t_end = years * YEAR_S
     y, out, _ = _run(acm, torch, net, y0, T, t_end, q_max=q_max)
-    ref, env, steps = oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=8, q_max=q_max)
+    ref, env, steps = oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=32, q_max=q_max)
     assert out["status"].tolist() == ref["status"].tolist() == [0] * len(T)
     ok = _agree(y, ref["y"], envelope=env)
     assert ok.all(), np.argwhere(~ok)[:5]
