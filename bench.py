@@ -99,6 +99,43 @@ def cpu_baseline(net, cells, seconds):
                       f"({dt:.1f} s, {threads} threads)"}
 
 
+# Sources that make up the Jacobian kernel: the HBM traffic recorded under
+# profiles/ is used only while they are unchanged.
+JAC_SOURCES = ("paper_2312_04998_amd/csrc/kernels_chem.hip", "paper_2312_04998_amd/csrc/devchem.h",
+               "paper_2312_04998_amd/csrc/devnet.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_jac_470x4600_65536_hbm_traffic.md")
+
+
+def jac_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in JAC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(cells, nnz_j):
+    """HBM bytes per k_jac launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy of known size),
+    or None when the summary is missing, was taken on another workload, or
+    the kernel's sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    try:
+        if (int(kv["cells"]) != cells or int(kv["nnz_j"]) != nnz_j
+                or kv["kernel_source_sha256"] != jac_source_digest()):
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def integration_legs(args, torch, acm, net, cells):
     """Batched BDF (one persistent workgroup per slot, device cell queue)
     on the first --int-cells cells against the plain per-cell loop timed on
@@ -299,12 +336,7 @@ def main():
 
     jac_ms = kern["jac"]["ms"]
     achieved = bytes_of["jac"] / (jac_ms * 1e-3) / 1e9
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "jac_hbm_traffic.json")
-    if os.path.exists(tpath):
-        tr = json.load(open(tpath))
-        if tr.get("nnz_j") == N.nnz_j and tr.get("cells") == C:
-            traffic = tr.get("bytes_per_launch")
+    traffic = measured_traffic(C, N.nnz_j)
     out = {
         "metric": "RHS evals (cells×reactions)/s + integrated cells/s at rtol 1e-6 vs plain",
         "value": C * nr / (ms_step * 1e-3),
