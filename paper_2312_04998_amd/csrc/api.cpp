@@ -60,7 +60,7 @@ const T *at(void *base, size_t off) {
 
 struct SchedOff {
   size_t seg_out, seg_chunk, chunk_ptr, chunk_dst, multi_out, multi_slot, items, slice_ptr,
-      sell_chunk, sell_len, sell_items, coo_out, run_mask, run_slot, seg_run;
+      sell_chunk, sell_len, sell_dst, sell_items, coo_out, run_items, run_mask, run_slot, seg_run;
 };
 
 static_assert(ac::RUN_LEN == ac::RUN_ITEMS, "host and device run lengths differ");
@@ -77,8 +77,10 @@ SchedOff add_sched(Packer &p, const ac::Schedule &s) {
   o.slice_ptr = p.add(s.slice_ptr);
   o.sell_chunk = p.add(s.sell_chunk);
   o.sell_len = p.add(s.sell_len);
+  o.sell_dst = p.add(s.sell_dst);
   o.sell_items = p.add(s.sell_items);
   o.coo_out = p.add(s.coo_out);
+  o.run_items = p.add(s.run_items);
   o.run_mask = p.add(s.run_mask);
   o.run_slot = p.add(s.run_slot);
   o.seg_run = p.add(s.seg_run);
@@ -104,10 +106,12 @@ ac::DSched dev_sched(void *b, const ac::Schedule &s, const SchedOff &o) {
   d.slice_ptr = at<int32_t>(b, o.slice_ptr);
   d.sell_chunk = at<int32_t>(b, o.sell_chunk);
   d.sell_len = at<int32_t>(b, o.sell_len);
+  d.sell_dst = at<int32_t>(b, o.sell_dst);
   d.sell_items = at<uint32_t>(b, o.sell_items);
   d.coo_out = at<int32_t>(b, o.coo_out);
   d.n_run = s.n_run;
   d.n_rslot = s.n_rslot;
+  d.run_items = at<uint4>(b, o.run_items);
   d.run_mask = at<uint32_t>(b, o.run_mask);
   d.run_slot = at<int32_t>(b, o.run_slot);
   d.seg_run = at<int32_t>(b, o.seg_run);

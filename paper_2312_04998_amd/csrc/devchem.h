@@ -23,6 +23,17 @@ __device__ __forceinline__ double term(uint32_t it, const double *__restrict__ A
   return v;
 }
 
+// acc + one packed term. Schedules of S itself (no density factor, HASB =
+// false) apply the coefficient inside a fused multiply-add: for the usual
+// power-of-two coefficients coef * A[j] is exact, so this rounds exactly like
+// the separate multiply and add, with two fewer instructions per term.
+template <bool HASB>
+__device__ __forceinline__ double term_add(double acc, uint32_t it, const double *__restrict__ A,
+                                           const double *__restrict__ ys) {
+  if (!HASB) return fma(double(int32_t(it) >> 27), A[it & 0xFFFFu], acc);
+  return __dadd_rn(acc, term(it, A, ys));
+}
+
 template <bool STREAM>
 __device__ __forceinline__ void put(double *p, double v) {
   if (STREAM) __builtin_nontemporal_store(v, p);
@@ -30,12 +41,13 @@ __device__ __forceinline__ void put(double *p, double v) {
 }
 
 // Chunk sums of a schedule: single-chunk segments go straight to out,
-// split segments leave partials in `part` for segsum_finish. Sums are
-// left to right with plain (uncontracted) adds, so CSR and SELL give the
-// same bits. SELL lanes of a slice loop to the slice width (wave-uniform)
-// with UNROLL term loads issued before they are consumed; IDENT marks a
-// schedule whose positions are its chunk ids (sigma = 1).
-template <int NT, int LAYOUT, bool IDENT, bool STREAM>
+// split segments leave partials in `part` for segsum_finish. Every chunk
+// is summed left to right with the same operations in both layouts, so
+// CSR and SELL give the same bits. SELL lanes of a slice loop to the slice
+// width (wave-uniform) with UNROLL term loads issued before they are
+// consumed; a slice position's length and destination are stored per
+// position, so a wave reads them contiguously.
+template <int NT, int LAYOUT, bool STREAM, bool HASB = true>
 __device__ __forceinline__ void segsum_chunks(const DSched &s, const double *__restrict__ A,
                                               const double *__restrict__ ys, double *part,
                                               double *__restrict__ out) {
@@ -57,8 +69,7 @@ __device__ __forceinline__ void segsum_chunks(const DSched &s, const double *__r
         const int base = ok ? s.slice_ptr[sl] : 0;
         width[p] = ok ? (s.slice_ptr[sl + 1] - base) / SELL_C : 0;
         len[p] = ok ? s.sell_len[pos] : 0;
-        const int ch = !ok ? -1 : (IDENT ? (pos < s.n_chunk ? pos : -1) : s.sell_chunk[pos]);
-        dst[p] = ch >= 0 ? s.chunk_dst[ch] : INT_MIN;
+        dst[p] = ok ? s.sell_dst[pos] : INT_MIN;
         it[p] = s.sell_items + base + (ok ? pos - sl * SELL_C : 0);
       }
       int wmax = 0;
@@ -77,10 +88,8 @@ __device__ __forceinline__ void segsum_chunks(const DSched &s, const double *__r
 #pragma unroll
         for (int p = 0; p < SELL_P; ++p)
 #pragma unroll
-          for (int u = 0; u < UNROLL; ++u) {
-            const double t = term(v[p][u], A, ys);
-            if (k0 + u < len[p]) acc[p] = __dadd_rn(acc[p], t);
-          }
+          for (int u = 0; u < UNROLL; ++u)
+            if (k0 + u < len[p]) acc[p] = term_add<HASB>(acc[p], v[p][u], A, ys);
       }
 #pragma unroll
       for (int p = 0; p < SELL_P; ++p) {
@@ -99,10 +108,8 @@ __device__ __forceinline__ void segsum_chunks(const DSched &s, const double *__r
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) v[u] = (k0 + u < p1) ? s.items[k0 + u] : PAD_ITEM;
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-          const double t = term(v[u], A, ys);
-          if (k0 + u < p1) acc = __dadd_rn(acc, t);
-        }
+        for (int u = 0; u < UNROLL; ++u)
+          if (k0 + u < p1) acc = term_add<HASB>(acc, v[u], A, ys);
       }
       const int d = s.chunk_dst[ch];
       if (d >= 0) put<STREAM>(out + d, acc);
@@ -114,18 +121,19 @@ __device__ __forceinline__ void segsum_chunks(const DSched &s, const double *__r
 // Equal-run partials: lane t sums the RUN_ITEMS items of run t left to
 // right, closing a partial (into part, numbered from run_slot[t]) wherever
 // the run's mask marks a new segment. All of a run's items are requested
-// with four 16-byte loads before any is used.
-template <int NT>
+// with eight 16-byte loads before any is used; runs are interleaved in
+// blocks of 64, so each load of a wave reads 1 KB of contiguous memory.
+template <int NT, bool HASB = true>
 __device__ __forceinline__ void runsum_partials(const DSched &s, const double *__restrict__ A,
                                                 const double *__restrict__ ys, double *part) {
   for (int t = threadIdx.x; t < s.n_run; t += NT) {
     const uint32_t mask = s.run_mask[t];
     int slot = s.run_slot[t];
     const int len = s.n_item - t * RUN_ITEMS < RUN_ITEMS ? s.n_item - t * RUN_ITEMS : RUN_ITEMS;
-    const uint4 *it4 = reinterpret_cast<const uint4 *>(s.items + size_t(t) * RUN_ITEMS);
+    const uint4 *it4 = s.run_items + size_t(t >> 6) * (RUN_ITEMS / 4) * 64 + (t & 63);
     uint4 w[RUN_ITEMS / 4];
 #pragma unroll
-    for (int q = 0; q < RUN_ITEMS / 4; ++q) w[q] = it4[q];
+    for (int q = 0; q < RUN_ITEMS / 4; ++q) w[q] = it4[q * 64];
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < RUN_ITEMS; ++k) {
@@ -136,7 +144,7 @@ __device__ __forceinline__ void runsum_partials(const DSched &s, const double *_
           part[slot++] = acc;
           acc = 0.0;
         }
-        acc = __dadd_rn(acc, term(it, A, ys));
+        acc = term_add<HASB>(acc, it, A, ys);
       }
     }
     if (len > 0) part[slot] = acc;
@@ -167,7 +175,7 @@ __device__ __forceinline__ void segsum_finish(const DSched &s, const double *par
 }
 
 // Full segmented sum (partials in LDS, so a barrier sits in between).
-template <int NT, int LAYOUT>
+template <int NT, int LAYOUT, bool HASB = true>
 __device__ __forceinline__ void segsum(const DSched &s, const double *A, const double *ys,
                                        double *part, double *out) {
   if (LAYOUT == LAYOUT_COO) {
@@ -175,18 +183,18 @@ __device__ __forceinline__ void segsum(const DSched &s, const double *A, const d
     for (int i = threadIdx.x; i < s.n_seg; i += NT) part[i] = 0.0;
     __syncthreads();
     for (int p = threadIdx.x; p < s.n_item; p += NT)
-      atomicAdd(&part[s.coo_out[p]], term(s.items[p], A, ys));
+      atomicAdd(&part[s.coo_out[p]], term_add<HASB>(0.0, s.items[p], A, ys));
     __syncthreads();
     for (int i = threadIdx.x; i < s.n_seg; i += NT) out[i] = part[i];
     return;
   }
   if (LAYOUT == LAYOUT_RUNS) {
-    runsum_partials<NT>(s, A, ys, part);
+    runsum_partials<NT, HASB>(s, A, ys, part);
     __syncthreads();
     runsum_finish<NT, false>(s, part, out);
     return;
   }
-  segsum_chunks<NT, LAYOUT, false, false>(s, A, ys, part, out);
+  segsum_chunks<NT, LAYOUT, false, HASB>(s, A, ys, part, out);
   __syncthreads();
   segsum_finish<NT, false>(s, part, out);
 }
@@ -203,7 +211,7 @@ struct Rx {
 };
 
 __device__ __forceinline__ Rx load_rx(const DNet &n, int j) {
-  const uint4 a = n.rxpack[4 * j], b = n.rxpack[4 * j + 1];
+  const uint4 a = n.rxpack[j], b = n.rxpack[n.nr + j];
   Rx r;
   r.la = __hiloint2double(int(a.y), int(a.x));
   r.beta = __hiloint2double(int(a.w), int(a.z));

@@ -15,10 +15,11 @@ struct DSched {
   const int32_t *seg_out, *seg_chunk, *chunk_ptr, *chunk_dst, *multi_out, *multi_slot;
   const uint32_t *items;
   int sell_c, n_slice;
-  const int32_t *slice_ptr, *sell_chunk, *sell_len;
+  const int32_t *slice_ptr, *sell_chunk, *sell_len, *sell_dst;
   const uint32_t *sell_items;
   const int32_t *coo_out;
   int n_run, n_rslot;
+  const uint4 *run_items;      // interleaved per 64-run block (see runsum_partials)
   const uint32_t *run_mask;
   const int32_t *run_slot, *seg_run;
 };
@@ -27,7 +28,7 @@ struct DNet {
   int ns, nr, nnz_j, layout, block;
   const double *log_alpha, *beta, *gamma;
   const uint32_t *rpair;       // reactant a | b << 16 (0xFFFF none)
-  const uint4 *rxpack;         // 4 x uint4 per reaction: (la, beta) (gamma, rpair) (S column)
+  const uint4 *rxpack;         // planes of nr words: (la, beta) | (gamma, rpair) | S column
   const int32_t *s_col_ptr, *s_row, *s_cval;   // CCS of S
   DSched rhs, jac, gy, jtail;
   const uint32_t *jhead0, *jhead1, *jtaildesc;

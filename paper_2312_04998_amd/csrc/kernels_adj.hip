@@ -103,7 +103,7 @@ __device__ __forceinline__ void cell_vjp(CellCtx &cx, const double *y, const dou
     for (int u2 = 0; u2 < U; ++u2) {
       const int j = j0 + u2 * NT;
       const bool ok = j < n.nr;
-      col[u2] = ok ? n.rxpack[4 * j + 2] : make_uint4(~0u, ~0u, ~0u, ~0u);
+      col[u2] = ok ? n.rxpack[2 * n.nr + j] : make_uint4(~0u, ~0u, ~0u, ~0u);
       pr[u2] = ok ? n.rpair[j] : 0u;
       kv[u2] = ok ? cx.kg[j] : 0.0;
     }
@@ -126,7 +126,7 @@ __device__ __forceinline__ void cell_vjp(CellCtx &cx, const double *y, const dou
     }
   }
   __syncthreads();
-  segsum_chunks<NT, LAYOUT_SELL, false, false>(n.gy, kw, y, part, u);
+  segsum_chunks<NT, LAYOUT_SELL, false>(n.gy, kw, y, part, u);
   __syncthreads();
   segsum_finish<NT, false>(n.gy, part, u);
   __syncthreads();

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(NT) void k_rhs(DNet n, const double *__restrict__ l
                         [&](int j, double kj, uint32_t pair) { rs[j] = reaction_rate(pair, kj, ys); });
     }
     __syncthreads();
-    segsum<NT, LAYOUT>(n.rhs, rs, ys, part, dydt + c * ns);
+    segsum<NT, LAYOUT, false>(n.rhs, rs, ys, part, dydt + c * ns);   // rows of S: no density factor
     __syncthreads();
   }
 }
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(NT) void k_vjp(DNet n, const double *__restrict__ l
     cell_temperature(T[c], L, invT);
     __syncthreads();
     for_reactions<NT>(n, la_over, L, invT, [&](int j, double kj, uint32_t pair) {
-      const uint4 col = n.rxpack[4 * j + 2];
+      const uint4 col = n.rxpack[2 * n.nr + j];
       const uint32_t w4[4] = {col.x, col.y, col.z, col.w};
       double w = 0.0;
 #pragma unroll
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(NT) void k_vjp(DNet n, const double *__restrict__ l
     __syncthreads();
     if (gy) {
       double *out = gy + c * ns;
-      segsum_chunks<NT, LAYOUT_SELL, false, false>(n.gy, kw, ys, part, out);
+      segsum_chunks<NT, LAYOUT_SELL, false>(n.gy, kw, ys, part, out);
       __syncthreads();
       segsum_finish<NT, false>(n.gy, part, out);
     }

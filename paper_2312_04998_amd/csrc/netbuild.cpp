@@ -2,6 +2,7 @@
 #include "netbuild.h"
 
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -167,7 +168,19 @@ void build_schedule(const std::vector<std::vector<uint32_t>> &seg_items,
     s.n_rslot = slot;
   }
   const uint32_t pad_item = pack_item(0, -1, 0);
-  s.items.resize(size_t(s.n_run) * RUN_LEN, pad_item);
+  {
+    const int nblk = (s.n_run + 63) / 64;
+    s.run_items.assign(size_t(nblk) * 64 * RUN_LEN, pad_item);
+    for (int t = 0; t < s.n_run; ++t) {
+      const int blk = t / 64, l = t % 64;
+      for (int k = 0; k < RUN_LEN; ++k) {
+        const int i = t * RUN_LEN + k;
+        if (i >= s.n_item) break;
+        const size_t w = (size_t(blk) * (RUN_LEN / 4) + k / 4) * 64 + l;
+        s.run_items[w * 4 + k % 4] = s.items[i];
+      }
+    }
+  }
 
   // SELL-C-sigma: positions are chunk ids sorted by length (descending,
   // stable) inside windows of sigma chunks, grouped into slices of C.
@@ -185,6 +198,7 @@ void build_schedule(const std::vector<std::vector<uint32_t>> &seg_items,
   s.slice_ptr.assign(1, 0);
   s.sell_chunk.assign(size_t(s.n_slice) * sell_c, -1);
   s.sell_len.assign(size_t(s.n_slice) * sell_c, 0);
+  s.sell_dst.assign(size_t(s.n_slice) * sell_c, INT32_MIN);
   for (int sl = 0; sl < s.n_slice; ++sl) {
     int width = 0;
     for (int l = 0; l < sell_c; ++l) {
@@ -192,6 +206,7 @@ void build_schedule(const std::vector<std::vector<uint32_t>> &seg_items,
       if (p < s.n_chunk) {
         s.sell_chunk[p] = pos[p];
         s.sell_len[p] = clen(pos[p]);
+        s.sell_dst[p] = s.chunk_dst[pos[p]];
         width = std::max(width, s.sell_len[p]);
       }
     }
@@ -375,19 +390,23 @@ std::string build_network(int ns, int nr, const int32_t *reactants, const int32_
     H.jtail.multi_slot.assign(1, 0);
   }
   build_schedule(gyseg, H.perm, chunk, sell_c, 1 << 30, H.gy);
-  // packed per-reaction record (see HostNet::rxpack)
-  H.rxpack.assign(size_t(nr) * 16, 0u);
+  // packed per-reaction records (see HostNet::rxpack), three planes of nr
+  // 16-byte words so that consecutive reactions are contiguous
+  H.rxpack.assign(size_t(nr) * 12, 0u);
   for (int j = 0; j < nr; ++j) {
-    uint32_t *r = &H.rxpack[size_t(j) * 16];
-    double par[3] = {H.log_alpha[j], H.beta[j], H.gamma[j]};
-    std::memcpy(r, par, sizeof(par));
-    r[6] = H.rpair[j];
+    uint32_t *p0 = &H.rxpack[size_t(j) * 4];
+    uint32_t *p1 = &H.rxpack[(size_t(nr) + j) * 4];
+    uint32_t *p2 = &H.rxpack[(size_t(2) * nr + j) * 4];
+    const double la_b[2] = {H.log_alpha[j], H.beta[j]};
+    std::memcpy(p0, la_b, sizeof(la_b));
+    std::memcpy(p1, &H.gamma[j], sizeof(double));
+    p1[2] = H.rpair[j];
     uint16_t half[8];
     for (int q = 0; q < 8; ++q) half[q] = 0xFFFF;
     int q = 0;
     for (int p = H.s_col_ptr[j]; p < H.s_col_ptr[j + 1]; ++p)
       half[q++] = uint16_t(H.s_row[p] | ((H.s_cval[p] & 31) << 11));
-    std::memcpy(r + 8, half, sizeof(half));
+    std::memcpy(p2, half, sizeof(half));
   }
   *code = AC_OK;
   return "";

@@ -38,6 +38,7 @@ struct Schedule {
   std::vector<int32_t> slice_ptr;  // [n_slice+1] offsets into sell_items
   std::vector<int32_t> sell_chunk; // [n_slice*sell_c] chunk id at a position, -1 = pad
   std::vector<int32_t> sell_len;   // [n_slice*sell_c] items of that chunk (0 for pads)
+  std::vector<int32_t> sell_dst;   // [n_slice*sell_c] chunk_dst of that chunk (INT32_MIN for pads)
   std::vector<uint32_t> sell_items;
   // COO: output index of every item (CSR order)
   std::vector<int32_t> coo_out;
@@ -48,6 +49,10 @@ struct Schedule {
   // (traversal order) owns the consecutive partials seg_run[2s] ..
   // seg_run[2s] + seg_run[2s+1] - 1.
   int n_run = 0, n_rslot = 0;
+  // items of the runs, interleaved so that lane l of a 64-run block reads its
+  // 16-byte word q at ((block * RUN_LEN / 4 + q) * 64 + l): a wave's loads
+  // are contiguous
+  std::vector<uint32_t> run_items;
   std::vector<uint32_t> run_mask;
   std::vector<int32_t> run_slot;   // [n_run]
   std::vector<int32_t> seg_run;    // [2 n_seg]
@@ -60,8 +65,9 @@ struct HostNet {
   // reaction data
   std::vector<double> log_alpha, beta, gamma;
   std::vector<uint32_t> rpair;        // reactant a | b << 16, 0xFFFF = none
-  // per reaction: ln alpha, beta, gamma, rpair, and the net column of S as up
-  // to 8 16-bit (species | coef << 11) halves (0xFFFF = none), 64 bytes
+  // per reaction, in three planes of nr 16-byte words: (ln alpha, beta),
+  // (gamma, rpair, 0), and the net column of S as up to 8 16-bit
+  // (species | coef << 11) halves (0xFFFF = none)
   std::vector<uint32_t> rxpack;
   // S in CSR (natural rows, reactions ascending) and CCS (per reaction)
   std::vector<int32_t> s_row_ptr, s_col, s_val;
