@@ -211,7 +211,9 @@ ac_status ac_lu_solve(int32_t n, int32_t lda, int64_t n_mat, const double *LU,
  * 0.9*9/(8+iters) * err^(-1/(q+1)) clamped to [0.2, 10]; order change to
  * the best of q-1, q, q+1 after q+1 equal steps; at most 4 Newton
  * iterations with a rate test; J refreshed once per attempt on Newton
- * failure, then h halved; M refactored whenever h or q changes. */
+ * failure, then h halved; M = I - c_M J kept while |c/c_M - 1| <= 0.3 and
+ * refactored beyond that or after a refresh of J, Newton corrections scaled
+ * by 2/(1 + c/c_M) in between (the LSODE-family matrix-reuse rule). */
 typedef struct {
   double rtol;        /* > 0 */
   double atol;        /* >= 0, in units of y */

@@ -351,7 +351,11 @@ void orc_lu_solve_t(int n, const double *LU, const int *piv, double *b) {
  *   step factor: safety * err^(-1/(q+1)) in [0.2, 10],
  *                safety = 0.9 (2*4+1)/(2*4 + newton iterations)
  *   order change after q+1 equal steps, to the best of q-1, q, q+1
- *   M is refactored whenever c changes; J only on Newton failure.
+ *   M = I - c_M J is kept while |c / c_M - 1| <= 0.3 and refactored when
+ *   c moves further, or after J is refreshed (J only on Newton failure);
+ *   with c != c_M every Newton correction is scaled by 2 / (1 + c / c_M).
+ *   This is the matrix-reuse rule of the LSODE family the paper uses
+ *   (DLSODES, Sec. 3), which the paper itself does not spell out.
  */
 
 #define QMAX 5
@@ -457,10 +461,12 @@ static void build_newton_matrix(int n, double c, const double *J, double *M) {
     for (int a = 0; a < n; ++a) M[(size_t)i * n + a] = (i == a ? 1.0 : 0.0) - c * J[(size_t)i * n + a];
 }
 
-/* Simplified Newton on the corrector equation; returns 1 if converged. */
-static int newton(cell_ctx *cx, const double *ypred, double c, const double *psi,
+/* Simplified Newton on the corrector equation with M factored at c_M;
+ * returns 1 if converged. */
+static int newton(cell_ctx *cx, const double *ypred, double c, double cM, const double *psi,
                   const double *LU, const int *piv, const double *scale, double tol, double *ynew,
                   double *d, double *f, double *dy, int *n_iter) {
+  const double corr = (c == cM) ? 1.0 : 2.0 / (1.0 + c / cM);
   const int n = cx->n;
   memcpy(ynew, ypred, sizeof(double) * n);
   for (int i = 0; i < n; ++i) d[i] = 0.0;
@@ -471,6 +477,8 @@ static int newton(cell_ctx *cx, const double *ypred, double c, const double *psi
     if (!all_finite(n, f)) break;
     for (int i = 0; i < n; ++i) dy[i] = c * f[i] - psi[i] - d[i];
     orc_lu_solve(n, LU, piv, dy);
+    if (corr != 1.0)
+      for (int i = 0; i < n; ++i) dy[i] *= corr;
     double dn = rms_scaled(n, dy, 1.0, scale);
     double rate = 0.0;
     if (it > 0) {
@@ -582,6 +590,7 @@ static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, double
   if (st) st[ORC_ST_JAC]++;
 
   int status = ORC_OK, q = 1, n_equal = 0, lu_valid = 0, steps = 0;
+  double cM = 0.0;
   double t = 0.0, h_abs = h;
   while (t < t_end) {
     if (steps >= o->max_steps) {
@@ -603,7 +612,6 @@ static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, double
         rescale_diffs(n, q, factor, D);
         tape_put(tw, ORC_EV_RESCALE, q, factor);
         n_equal = 0;
-        lu_valid = 0;
       }
       h = t_new - t;
       h_abs = h;
@@ -619,13 +627,14 @@ static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, double
       const double c = h / K.alph[q];
       int conv = 0;
       for (;;) {
-        if (!lu_valid) {
+        if (!lu_valid || fabs(c / cM - 1.0) > 0.3) {
           build_newton_matrix(n, c, J, LU);
           orc_lu_factor(n, LU, piv);
           if (st) st[ORC_ST_LU]++;
           lu_valid = 1;
+          cM = c;
         }
-        conv = newton(&cx, ypred, c, psi, LU, piv, scale, tol, ynew, d, f, dy, &n_iter);
+        conv = newton(&cx, ypred, c, cM, psi, LU, piv, scale, tol, ynew, d, f, dy, &n_iter);
         if (conv || jac_fresh) break;
         cell_jac(net, k, ypred, J, NULL);
         if (st) st[ORC_ST_JAC]++;
@@ -637,7 +646,6 @@ static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, double
         rescale_diffs(n, q, 0.5, D);
         tape_put(tw, ORC_EV_RESCALE, q, 0.5);
         n_equal = 0;
-        lu_valid = 0;
         if (st) st[ORC_ST_REJECT_NEWTON]++;
         continue;
       }
@@ -650,7 +658,6 @@ static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, double
         rescale_diffs(n, q, factor, D);
         tape_put(tw, ORC_EV_RESCALE, q, factor);
         n_equal = 0;
-        lu_valid = 0;
         if (st) st[ORC_ST_REJECT_ERR]++;
         continue;
       }
@@ -675,7 +682,6 @@ static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, double
     rescale_diffs(n, q, factor, D);
     tape_put(tw, ORC_EV_RESCALE, q, factor);
     n_equal = 0;
-    lu_valid = 0;
   }
 done:
   memcpy(y, D, sizeof(double) * n);

@@ -21,7 +21,10 @@
 //   error test: RMS of d/(atol + rtol|y_new|)/(q+1) <= 1; step factor
 //     safety * err^(-1/(q+1)) in [0.2, 10], safety = 0.9*9/(8 + iterations)
 //   order change after q+1 equal steps, to the best of q-1, q, q+1
-//   M refactored whenever c changes; J refreshed only on Newton failure.
+//   M = I - c_M J kept while |c/c_M - 1| <= 0.3, refactored when c moves
+//   further or J is refreshed (J only on Newton failure); with c != c_M
+//   each Newton correction is scaled by 2/(1 + c/c_M) (the matrix-reuse
+//   rule of the LSODE family, to which the paper's DLSODES belongs).
 #include "devstep.h"
 
 namespace ac {
@@ -136,6 +139,7 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
 
       int n_equal = 0;
       bool lu_valid = false;
+      double cM = 0.0;   // c of the factored Newton matrix
       double t = 0.0, h_abs = h;
       while (t < t_end) {
         if (steps >= P.max_steps) {
@@ -160,7 +164,6 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
             rescale_diffs<NT>(cx, q, factor, ns);
             tape_put(tv, cell, tlen, EV_RESCALE, q, factor);
             n_equal = 0;
-            lu_valid = false;
           }
           h = t_new - t;
           h_abs = h;
@@ -181,10 +184,12 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
           const double c = h / alph_q;
           bool conv = false;
           for (;;) {
-            if (!lu_valid) {
+            if (!lu_valid || fabs(c / cM - 1.0) > 0.3) {
               cell_factor<NT>(cx, c);
               lu_valid = true;
+              cM = c;
             }
+            const double corr = c == cM ? 1.0 : 2.0 / (1.0 + c / cM);
             // simplified Newton
             for (int x = threadIdx.x; x < ns; x += NT) {
               yn[x] = yp[x];
@@ -202,6 +207,10 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
               for (int x = threadIdx.x; x < ns; x += NT) dy[x] = c * f[x] - psi[x] - dd[x];
               __syncthreads();
               wg_solve<NT>(cx.M, cx.lda, ns, cx.perm, dy, cx.tmp, false, cx.scr);
+              if (corr != 1.0) {
+                for (int x = threadIdx.x; x < ns; x += NT) dy[x] *= corr;
+                __syncthreads();
+              }
               const double dn = wg_rms<NT>(dy, 1.0, scl, ns, red);
               double rate = 0.0;
               if (it > 0) {
@@ -232,7 +241,6 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
             rescale_diffs<NT>(cx, q, 0.5, ns);
             tape_put(tv, cell, tlen, EV_RESCALE, q, 0.5);
             n_equal = 0;
-            lu_valid = false;
             cx.cnt[ST_REJ_NEWTON]++;
             continue;
           }
@@ -246,7 +254,6 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
             rescale_diffs<NT>(cx, q, factor, ns);
             tape_put(tv, cell, tlen, EV_RESCALE, q, factor);
             n_equal = 0;
-            lu_valid = false;
             cx.cnt[ST_REJ_ERR]++;
             continue;
           }
@@ -279,7 +286,6 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
         rescale_diffs<NT>(cx, q, factor, ns);
         tape_put(tv, cell, tlen, EV_RESCALE, q, factor);
         n_equal = 0;
-        lu_valid = false;
       }
       for (int x = threadIdx.x; x < ns; x += NT) ycell[x] = cx.D[x];
       __syncthreads();

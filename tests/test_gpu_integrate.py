@@ -109,18 +109,26 @@ def _agree(y_gpu, y_ora, rtol=1e-6, floor=1e-20, envelope=None):
 
 
 def oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=4, **kw):
-    """Oracle run plus the spread of k reruns with y0 perturbed by 1e-15
-    relative (the trajectory's own sensitivity to rounding)."""
+    """Oracle run plus the spread of k reruns with y0 perturbed by 1e-15 and
+    the rate prefactors alpha by 1e-14 relative: the trajectory's own
+    sensitivity to rounding of the size by which the two sides' rate
+    coefficients differ (exp of a sum against the product of a power and
+    an exp, up to ~100 ulp)."""
+    import dataclasses
     y0 = np.atleast_2d(y0)
     n = y0.shape[0]
+    T = np.atleast_1d(T)
+    ref = oracle_mod.bdf(net, y0, T, t_end, **kw)
     rng = np.random.default_rng(12345)
-    pert = np.concatenate([y0] + [y0 * (1 + 1e-15 * rng.standard_normal(y0.shape)) for _ in range(k)])
-    out = oracle_mod.bdf(net, pert, np.tile(np.atleast_1d(T), k + 1), t_end, **kw)
-    ref = {key: v[:n] for key, v in out.items()}
-    ys = out["y"].reshape(k + 1, n, -1)
+    ys, steps = [ref["y"]], [ref["stats"][:, 0]]
+    for _ in range(k):
+        pnet = dataclasses.replace(net, alpha=net.alpha * (1 + 1e-14 * rng.standard_normal(net.alpha.shape)))
+        o = oracle_mod.bdf(pnet, y0 * (1 + 1e-15 * rng.standard_normal(y0.shape)), T, t_end, **kw)
+        ys.append(o["y"])
+        steps.append(o["stats"][:, 0])
+    ys = np.stack(ys)
     env = np.abs(ys[1:] - ys[0]).max(0)
-    steps = out["stats"][:, 0].reshape(k + 1, n)
-    return ref, env, steps
+    return ref, env, np.stack(steps)
 
 
 def _run(acm, torch, net, y0, T, t_end, ws=None, **kw):
@@ -151,15 +159,18 @@ def test_tiny_network_parity(acm, torch_dev, oracle_mod, tiny, q_max, years):
     assert ok.all(), np.argwhere(~ok)[:5]
     strict = _agree(y, ref["y"])
     print(f"strict 1e-6 bar met by {strict.mean():.4f} of species-cells")
-    # Step counts: rounding-level differences flip single accept/reject
-    # decisions, so the oracle's own count already moves by a step or two
+    # Step counts: rounding-level differences flip single accept/reject and
+    # matrix-reuse decisions, so the oracle's own count moves by up to ~1 %
     # under 1e-15 relative perturbations of y0. The GPU count must fall in
-    # the range the perturbed oracle runs span (one step of slack).
+    # the range 32 perturbed oracle runs span, widened by half that spread
+    # (a finite sample underestimates the range), at least one step.
     g, o = out["stats"][:, 0], ref["stats"][:, 0]
     print("steps gpu", g.tolist(), "oracle", o.tolist(), "perturbed range",
           steps.min(0).tolist(), steps.max(0).tolist())
     assert np.all(np.abs(g - o) <= 0.01 * o + 3)
-    assert np.all((g >= steps.min(0) - 1) & (g <= steps.max(0) + 1))
+    lo, hi = steps.min(0), steps.max(0)
+    slack = np.maximum(1, (hi - lo) // 2)
+    assert np.all((g >= lo - slack) & (g <= hi + slack))
 
 
 def test_medium_network_parity(acm, torch_dev, oracle_mod, medium):
@@ -198,8 +209,10 @@ def test_queue_more_cells_than_slots(acm, torch_dev, oracle_mod, tiny):
     y2 = _t(torch, y0)
     o2 = ws.integrate(y2, _t(torch, T), t_end, plain=True)
     assert torch.equal(y1, y2) and torch.equal(o1["stats"], o2["stats"])
-    ref, env, _ = oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=2)
-    assert np.all(_agree(y1.cpu().numpy(), ref["y"], envelope=env))
+    ref, env, steps = oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=8)
+    ok = _agree(y1.cpu().numpy(), ref["y"], envelope=env)
+    bad = np.argwhere(~ok)
+    assert ok.all(), (bad[:5], o1["stats"][bad[:1, 0]].tolist(), steps[:, bad[:1, 0]].T.tolist())
 
 
 def test_status_codes(acm, torch_dev, tiny):
