@@ -39,10 +39,11 @@ struct AdjVecs {
 
 // Converged corrector for a recorded step (q, h): Newton on G(d) = 0 until
 // the update is at rounding level, then D advances. The Newton matrix
-// carries over from the previous step (refactored with the same Jacobian
-// when c changes, as the integrator does) and J is refreshed at the
-// current iterate whenever the contraction is slow; cM is the c of the
-// factored matrix, 0 when there is none (J is then formed at y_pred).
+// carries over from the previous step with the integrator's reuse rule
+// (refactored with the same Jacobian once |c/cM - 1| > 0.3, corrections
+// scaled by 2/(1 + c/cM) in between) and J is refreshed at the current
+// iterate whenever the contraction is slow; cM is the c of the factored
+// matrix, 0 when there is none (J is then formed at y_pred).
 // Every checkpointed segment starts from cM = 0, so a segment's replay
 // depends only on its checkpoint and is bitwise repeatable. The converged
 // y is left in v.yn. Stopping rules are the oracle's replay rules.
@@ -54,7 +55,7 @@ __device__ __forceinline__ void replay_step(CellCtx &cx, const AdjVecs &v, int q
   for (int x = threadIdx.x; x < ns; x += NT) v.dd[x] = 0.0;
   __syncthreads();
   if (cM == 0.0) cell_jac<NT>(cx, v.yp);
-  if (cM != c) {
+  if (cM == 0.0 || fabs(c / cM - 1.0) > 0.3) {
     cell_factor<NT>(cx, c);
     cM = c;
   }
@@ -66,6 +67,7 @@ __device__ __forceinline__ void replay_step(CellCtx &cx, const AdjVecs &v, int q
     if (refresh) {
       cell_jac<NT>(cx, v.yn);
       cell_factor<NT>(cx, c);
+      cM = c;
       refresh = false;
     }
     cell_rhs<NT>(cx, v.yn, v.f);
@@ -73,6 +75,11 @@ __device__ __forceinline__ void replay_step(CellCtx &cx, const AdjVecs &v, int q
     for (int x = threadIdx.x; x < ns; x += NT) v.dy[x] = -(v.dd[x] - c * v.f[x] + v.psi[x]);
     __syncthreads();
     wg_solve<NT>(cx.M, cx.lda, ns, cx.perm, v.dy, cx.tmp, false, cx.scr);
+    if (c != cM) {
+      const double corr = 2.0 / (1.0 + c / cM);
+      for (int x = threadIdx.x; x < ns; x += NT) v.dy[x] *= corr;
+      __syncthreads();
+    }
     const double dn = wg_rms<NT>(v.dy, 1.0, v.scl, ns, cx.red);
     for (int x = threadIdx.x; x < ns; x += NT) v.dd[x] += v.dy[x];
     __syncthreads();
