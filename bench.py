@@ -136,6 +136,47 @@ def measured_traffic(cells, nnz_j):
         return None
 
 
+def lu_leg(torch, acm, net, cells, n_mat=256):
+    """Batched dense LU and solves of Newton matrices I - c J (470 x 470,
+    one matrix per workgroup), the integrator's linear algebra in
+    isolation: 2n^3/3 flops per factorisation against the FP64 matrix-core
+    peak, n^2 doubles read per solve against HBM."""
+    dev = torch.device("cuda:0")
+    N = acm.Network.from_synth(net)
+    ns = net.n_species
+    y = torch.from_numpy(cells.y0[:n_mat].copy()).to(dev)
+    T = torch.from_numpy(cells.T[:n_mat].copy()).to(dev)
+    jv = N.jac(y, T)
+    rp, col = N.jac_pattern()
+    rows = torch.from_numpy(np.repeat(np.arange(ns), np.diff(rp))).to(dev)
+    cols = torch.from_numpy(col.astype(np.int64)).to(dev)
+    lda = (ns + 15) // 16 * 16
+    A0 = torch.zeros((n_mat, ns, lda), dtype=torch.float64, device=dev)
+    A0[:, torch.arange(ns, device=dev), torch.arange(ns, device=dev)] = 1.0
+    A0[:, rows, cols] -= 1e7 * jv
+    piv = torch.empty((n_mat, ns), dtype=torch.int32, device=dev)
+    b = torch.randn((n_mat, ns), dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(1))
+    A = A0.clone()
+    acm.ac_lu_factor(A, piv)
+    acm.ac_lu_solve(A, piv, b.clone())
+    torch.cuda.synchronize()
+    tm = Timer(torch)
+    for _ in range(3):
+        A.copy_(A0)
+        tm.run("lu", lambda: acm.ac_lu_factor(A, piv))
+        bb = b.clone()
+        tm.run("solve", lambda: acm.ac_lu_solve(A, piv, bb))
+    torch.cuda.synchronize()
+    lu_ms, sv_ms = tm.mean_ms("lu"), tm.mean_ms("solve")
+    flops = n_mat * 2.0 * ns ** 3 / 3.0
+    sbytes = n_mat * 8.0 * ns * ns
+    return {"lu": {"matrices": n_mat, "n": ns, "c": 1e7, "ms": lu_ms,
+                   "TFLOPs": flops / (lu_ms * 1e-3) / 1e12,
+                   "mfma_frac": flops / (lu_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                   "solve_ms": sv_ms, "solve_GBps": sbytes / (sv_ms * 1e-3) / 1e9,
+                   "solve_hbm_frac": sbytes / (sv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+
+
 def integration_legs(args, torch, acm, net, cells):
     """Batched BDF (one persistent workgroup per slot, device cell queue)
     on the first --int-cells cells against the plain per-cell loop timed on
@@ -361,6 +402,7 @@ def main():
         "block_table_ms": blocks,
     }
     if not args.no_int:
+        out.update(lu_leg(torch, acm, net, cells))
         out.update(integration_legs(args, torch, acm, net, cells))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(net, cells, args.cpu_seconds)
