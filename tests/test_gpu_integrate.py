@@ -34,7 +34,7 @@ def _t(torch, a, dtype=None):
 
 # ------------------------------------------------------------------ LU
 
-@pytest.mark.parametrize("n", [1, 5, 16, 33, 100, 470])
+@pytest.mark.parametrize("n", [1, 5, 16, 33, 100, 470, 513, 700, 1024])
 def test_lu_matches_oracle(acm, torch_dev, oracle_mod, n):
     torch = torch_dev
     rng = np.random.default_rng(n)
@@ -191,6 +191,23 @@ def test_medium_network_parity(acm, torch_dev, oracle_mod, medium):
     E = net.composition.astype(np.float64).T
     drift = np.abs(y @ E.T - y0 @ E.T) / (y0 @ np.abs(E).T)
     assert drift.max() < 1e-7
+
+
+def test_large_network_parity(acm, torch_dev, oracle_mod):
+    """700 species / 8000 reactions with grain-surface terms: the Newton
+    matrix has more rows than the workgroup has threads (two panel rows per
+    thread) and the LDS working set exceeds 64 KB. One cell, 100 yr."""
+    torch = torch_dev
+    net, _ = synthnet.workload("large", n_cells=1)
+    cells = synthnet.make_cells(net, 2, synthnet.SEED_BASE + 4)
+    y0, T = cells.y0[:1], cells.T[:1]
+    t_end = 1e2 * YEAR_S
+    y, out, _ = _run(acm, torch, net, y0, T, t_end)
+    ref, env, steps = oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=2)
+    assert out["status"].tolist() == ref["status"].tolist() == [0]
+    ok = _agree(y, ref["y"], envelope=env)
+    assert ok.all(), np.argwhere(~ok)[:5]
+    print("steps gpu", out["stats"][:, 0].tolist(), "oracle", steps[:, 0].tolist())
 
 
 def test_queue_more_cells_than_slots(acm, torch_dev, oracle_mod, tiny):

@@ -234,3 +234,13 @@ def test_schedules_cover_every_term(acm, medium_net):
         reac = set(int(a) for a in net.reactants[j] if a >= 0)
         count += len(reac) * int((S[:, j] != 0).sum())
     assert N.n_contrib == count
+
+
+def test_lu_size_limit(acm):
+    """Dense LU panels live in one workgroup (two rows per thread): n <= 1024."""
+    import torch
+    A = torch.zeros((1, 1025, 1025), dtype=torch.float64)
+    piv = torch.zeros((1, 1025), dtype=torch.int32)
+    with pytest.raises(acm.AstrochemError) as e:
+        acm.ac_lu_factor(A, piv, stream=0)   # rejected on the host, nothing launched
+    assert e.value.status == acm.AC_ELIMIT
