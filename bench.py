@@ -36,10 +36,11 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--cells", type=int, default=65536)
-    p.add_argument("--layout", default="sell")
-    p.add_argument("--ordering", default="nnz")
-    p.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library default)")
-    p.add_argument("--no-table", action="store_true", help="skip the layout x ordering table")
+    p.add_argument("--layout", default="auto", help="sell|csr|runs|coo, or auto (autotuned)")
+    p.add_argument("--ordering", default="auto", help="nnz|natural|rcm, or auto (autotuned)")
+    p.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = autotuned)")
+    p.add_argument("--no-table", action="store_true",
+                   help="skip the autotuner (layout x ordering x block table); use sell/nnz/512")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--no-int", action="store_true", help="skip the integration legs")
@@ -115,11 +116,11 @@ def jac_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(cells, nnz_j):
+def measured_traffic(cells, nnz_j, block):
     """HBM bytes per k_jac launch from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy of known size),
-    or None when the summary is missing, was taken on another workload, or
-    the kernel's sources changed since."""
+    or None when the summary is missing, was taken on another workload or
+    workgroup size, or the kernel's sources changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -128,7 +129,7 @@ def measured_traffic(cells, nnz_j):
             k, v = line[2:].split(": ", 1)
             kv[k.strip()] = v.strip().strip("`")
     try:
-        if (int(kv["cells"]) != cells or int(kv["nnz_j"]) != nnz_j
+        if (int(kv["cells"]) != cells or int(kv["nnz_j"]) != nnz_j or int(kv["block"]) != block
                 or kv["kernel_source_sha256"] != jac_source_digest()):
             return None
         return int(kv["traffic_bytes_per_launch"])
@@ -284,7 +285,21 @@ def main():
     dev = torch.device("cuda:0")
     y = torch.from_numpy(cells.y0).to(dev)
     T = torch.from_numpy(cells.T).to(dev)
-    N = acm.Network.from_synth(net, layout=args.layout, ordering=args.ordering, block=args.block)
+    tune_table = {}
+    if args.no_table:
+        cfg = {"layout": "sell", "ordering": "nnz", "block": 512}
+    else:
+        from paper_2312_04998_amd.autotune import autotune
+        N, cfg, tab = autotune(net, y, T)
+        N.close()
+        tune_table = {f"{l}/{o}/{b}": round(ms, 4) for (l, o, b), ms in sorted(tab.items(), key=lambda kv: kv[1])}
+    if args.layout != "auto":
+        cfg["layout"] = args.layout
+    if args.ordering != "auto":
+        cfg["ordering"] = args.ordering
+    if args.block:
+        cfg["block"] = args.block
+    N = acm.Network.from_synth(net, **cfg)
     dydt = torch.empty_like(y)
     jv = torch.empty((args.cells, N.nnz_j), dtype=torch.float64, device=dev)
     k = torch.empty((args.cells, nr), dtype=torch.float64, device=dev)
@@ -345,39 +360,9 @@ def main():
                       "GBps": bytes_of[name] / (ms * 1e-3) / 1e9,
                       "hbm_frac": bytes_of[name] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
-    table = {}
-    blocks = {}
-    if not args.no_table:
-        for blk in (256, 512, 1024):
-            M = acm.Network.from_synth(net, layout=args.layout, ordering=args.ordering, block=blk)
-            for _ in range(2):
-                acm.ac_rhs(M, None, y, T, dydt)
-                acm.ac_jac(M, None, y, T, jv)
-            torch.cuda.synchronize()
-            tt = Timer(torch)
-            for _ in range(5):
-                tt.run("rhs", lambda: acm.ac_rhs(M, None, y, T, dydt))
-                tt.run("jac", lambda: acm.ac_jac(M, None, y, T, jv))
-                tt.run("vjp", lambda: acm.ac_vjp(M, None, y, T, v, gy, gl))
-            torch.cuda.synchronize()
-            blocks[str(blk)] = {kk: round(tt.mean_ms(kk), 4) for kk in ("rhs", "jac", "vjp")}
-            M.close()
-        for lay in ("csr", "sell", "coo"):
-            for order in ("natural", "nnz", "rcm"):
-                M = acm.Network.from_synth(net, layout=lay, ordering=order)
-                for _ in range(2):
-                    acm.ac_rhs(M, None, y, T, dydt)
-                torch.cuda.synchronize()
-                tt = Timer(torch)
-                for _ in range(5):
-                    tt.run("r", lambda: acm.ac_rhs(M, None, y, T, dydt))
-                torch.cuda.synchronize()
-                table[f"{lay}/{order}"] = round(C * nr / (tt.mean_ms("r") * 1e-3), 1)
-                M.close()
-
     jac_ms = kern["jac"]["ms"]
     achieved = bytes_of["jac"] / (jac_ms * 1e-3) / 1e9
-    traffic = measured_traffic(C, N.nnz_j)
+    traffic = measured_traffic(C, N.nnz_j, cfg["block"])
     out = {
         "metric": "RHS evals (cells×reactions)/s + integrated cells/s at rtol 1e-6 vs plain",
         "value": C * nr / (ms_step * 1e-3),
@@ -393,13 +378,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "470 species / 4600 reactions, 65,536 cells, RHS + Jacobian",
                    "n_species": ns, "n_reactions": nr, "cells": C, "nnz_s": N.nnz_s,
-                   "nnz_j": N.nnz_j, "layout": args.layout, "ordering": args.ordering},
+                   "nnz_j": N.nnz_j, "layout": cfg["layout"], "ordering": cfg["ordering"],
+                   "block": cfg["block"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_jac",
                      "bytes_per_launch": bytes_of["jac"], "avg_ms": jac_ms},
         "kernels": kern,
-        "rhs_layout_table": table,
-        "block_table_ms": blocks,
+        "autotune_ms_per_step": tune_table,
     }
     if not args.no_int:
         out.update(lu_leg(torch, acm, net, cells))

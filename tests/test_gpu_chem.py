@@ -212,3 +212,21 @@ def test_edge_cases(acm, torch_dev, oracle_mod):
     # bad shapes are caught before any launch
     with pytest.raises(ValueError):
         N.rhs(_t(torch, np.zeros((2, 4))), _t(torch, [1.0, 2.0]))
+
+
+def test_autotune_picks_a_working_configuration(acm, torch_dev, oracle_mod, medium_net, med_cells):
+    """The autotuner times every layout x ordering x block on the caller's
+    cells and returns the fastest network; that network's RHS and Jacobian
+    still match the oracle."""
+    torch = torch_dev
+    from paper_2312_04998_amd.autotune import autotune, LAYOUTS, ORDERINGS, BLOCKS
+    y, T = med_cells.y0[:256], med_cells.T[:256]
+    N, kw, table = autotune(medium_net, _t(torch, y), _t(torch, T), reps=2)
+    assert len(table) == len(LAYOUTS) * len(ORDERINGS) * len(BLOCKS)
+    assert table[(kw["layout"], kw["ordering"], kw["block"])] == min(table.values())
+    f = N.rhs(_t(torch, y[:40]), _t(torch, T[:40])).cpu().numpy()
+    ref, ab = oracle_mod.rhs(medium_net, y[:40], T[:40], with_abs=True)
+    _close(f, ref, ab)
+    jv = N.jac(_t(torch, y[:40]), _t(torch, T[:40])).cpu().numpy()
+    J, abJ = oracle_mod.jac_dense(medium_net, y[:40], T[:40], with_abs=True)
+    _close(jv, _jac_at_pattern(N, J), _jac_at_pattern(N, abJ))
