@@ -49,9 +49,22 @@ __global__ __launch_bounds__(NT) void k_rhs(DNet n, const double *__restrict__ l
     if (!PREK) cell_temperature(T[c], L, invT);
     __syncthreads();
     if (PREK) {
+      // every coefficient and reactant pair of a lane requested before use
+      constexpr int KU = 8;
       const double *kc = kin + c * nr;
-      for (int j = threadIdx.x; j < nr; j += NT)
-        rs[j] = reaction_rate(n.rpair[j], __builtin_nontemporal_load(kc + j), ys);
+      for (int j0 = threadIdx.x; j0 < nr; j0 += KU * NT) {
+        double kv[KU];
+        uint32_t pr[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+          const int j = j0 + u * NT;
+          kv[u] = j < nr ? __builtin_nontemporal_load(kc + j) : 0.0;
+          pr[u] = j < nr ? n.rpair[j] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < KU; ++u)
+          if (j0 + u * NT < nr) rs[j0 + u * NT] = reaction_rate(pr[u], kv[u], ys);
+      }
     } else {
       for_reactions<NT>(n, la_over, L, invT,
                         [&](int j, double kj, uint32_t pair) { rs[j] = reaction_rate(pair, kj, ys); });
