@@ -69,10 +69,13 @@ typedef enum {
                           sorted by length within windows of sell_sigma (SELL-C-sigma) */
   AC_LAYOUT_COO = 2,   /* coordinate triplets, scattered with LDS atomics
                           (summation order not reproducible run to run) */
-  AC_LAYOUT_RUNS = 3   /* CRS nonzeros cut into equal runs of 32 per lane
+  AC_LAYOUT_RUNS = 3,  /* CRS nonzeros cut into equal runs of 32 per lane
                           whatever the row lengths (merge-style partition); a
                           32-bit mask per run marks row starts, each row adds
                           its run partials in order */
+  AC_LAYOUT_CCS = 4    /* column by column: each reaction scatters S_ij R_j
+                          into its species with LDS atomics (order not
+                          reproducible run to run) */
 } ac_layout;
 
 /* Order in which species rows are traversed (Sec. 3 reorders rows by their

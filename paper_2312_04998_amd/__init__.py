@@ -18,12 +18,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libastrochem.so")
 
 AC_OK, AC_EINVAL, AC_ENOMEM, AC_EHIP, AC_EUNBALANCED, AC_ECAPACITY, AC_ELIMIT = range(7)
-AC_LAYOUT_CSR, AC_LAYOUT_SELL, AC_LAYOUT_COO, AC_LAYOUT_RUNS = 0, 1, 2, 3
+AC_LAYOUT_CSR, AC_LAYOUT_SELL, AC_LAYOUT_COO, AC_LAYOUT_RUNS, AC_LAYOUT_CCS = 0, 1, 2, 3, 4
 AC_ORDER_NATURAL, AC_ORDER_NNZ_DESC, AC_ORDER_RCM = 0, 1, 2
 AC_FMT_COO, AC_FMT_CCS, AC_FMT_CRS, AC_FMT_SELL = 0, 1, 2, 3
 AC_CELL_OK, AC_CELL_MAXSTEPS, AC_CELL_HMIN, AC_CELL_BADINPUT, AC_CELL_TAPE = 0, 1, 2, 3, 4
 LAYOUTS = {"csr": AC_LAYOUT_CSR, "sell": AC_LAYOUT_SELL, "coo": AC_LAYOUT_COO,
-           "runs": AC_LAYOUT_RUNS}
+           "runs": AC_LAYOUT_RUNS, "ccs": AC_LAYOUT_CCS}
 ORDERINGS = {"natural": AC_ORDER_NATURAL, "nnz": AC_ORDER_NNZ_DESC, "rcm": AC_ORDER_RCM}
 
 

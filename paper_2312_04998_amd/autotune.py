@@ -1,7 +1,7 @@
 """Autotuner for the chemistry kernels' launch shape.
 
 The RHS and Jacobian kernels take three build-time choices: the storage
-layout of S (CRS chunks, SELL-C-sigma, equal runs, COO), the species
+layout of S (CRS chunks, SELL-C-sigma, equal runs, COO, CCS), the species
 traversal order (natural, nnz-descending, reverse Cuthill-McKee) and the
 workgroup size (256, 512 or 1024 threads). Which combination is fastest
 depends on the network's shape and on the cell count, so `autotune` times
@@ -15,7 +15,7 @@ from typing import Dict, Iterable, Tuple
 
 from . import Network, ac_jac, ac_rhs
 
-LAYOUTS = ("sell", "csr", "runs", "coo")
+LAYOUTS = ("sell", "csr", "runs", "coo", "ccs")
 ORDERINGS = ("nnz", "natural", "rcm")
 BLOCKS = (512, 256, 1024)
 

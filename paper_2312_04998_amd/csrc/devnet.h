@@ -7,7 +7,7 @@
 
 namespace ac {
 
-constexpr int LAYOUT_CSR = 0, LAYOUT_SELL = 1, LAYOUT_COO = 2, LAYOUT_RUNS = 3;
+constexpr int LAYOUT_CSR = 0, LAYOUT_SELL = 1, LAYOUT_COO = 2, LAYOUT_RUNS = 3, LAYOUT_CCS = 4;
 constexpr int RUN_ITEMS = 32;   // items per run of the equal-run partition
 
 struct DSched {

@@ -45,6 +45,8 @@ __global__ __launch_bounds__(NT) void k_rhs(DNet n, const double *__restrict__ l
   double *part = rs + nr;
   for (int64_t c = blockIdx.x; c < n_cells; c += gridDim.x) {
     load_cell<NT>(y + c * ns, ys, ns);
+    if (LAYOUT == LAYOUT_CCS)
+      for (int i = threadIdx.x; i < ns; i += NT) part[i] = 0.0;
     double L = 0.0, invT = 0.0;
     if (!PREK) cell_temperature(T[c], L, invT);
     __syncthreads();
@@ -70,7 +72,26 @@ __global__ __launch_bounds__(NT) void k_rhs(DNet n, const double *__restrict__ l
                         [&](int j, double kj, uint32_t pair) { rs[j] = reaction_rate(pair, kj, ys); });
     }
     __syncthreads();
-    segsum<NT, LAYOUT, false>(n.rhs, rs, ys, part, dydt + c * ns);   // rows of S: no density factor
+    if (LAYOUT == LAYOUT_CCS) {
+      // column by column (Sec. 2.2's CCS traversal): every reaction adds
+      // S_ij R_j to each species of its packed net column, with LDS atomics
+      // (the order of additions varies from run to run)
+      for (int j = threadIdx.x; j < nr; j += NT) {
+        const uint4 col = n.rxpack[2 * nr + j];
+        const uint32_t w4[4] = {col.x, col.y, col.z, col.w};
+        const double r = rs[j];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const uint32_t h = (w4[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+          if (h != 0xFFFFu) atomicAdd(&part[h & 2047u], double(int32_t(h << 16) >> 27) * r);
+        }
+      }
+      __syncthreads();
+      double *out = dydt + c * ns;
+      for (int i = threadIdx.x; i < ns; i += NT) out[i] = part[i];
+    } else {
+      segsum<NT, LAYOUT, false>(n.rhs, rs, ys, part, dydt + c * ns);   // rows of S: no density factor
+    }
     __syncthreads();
   }
 }
@@ -228,7 +249,7 @@ static int grid_for(K kernel, int nt, size_t lds, int64_t n_cells) {
 }
 
 size_t rhs_lds_bytes(const DNet &n) {
-  const int extra = n.layout == LAYOUT_COO    ? n.ns
+  const int extra = (n.layout == LAYOUT_COO || n.layout == LAYOUT_CCS) ? n.ns
                     : n.layout == LAYOUT_RUNS ? n.rhs.n_rslot
                                               : n.rhs.n_slot;
   return sizeof(double) * size_t(n.ns + n.nr + (extra > 0 ? extra : 1));
@@ -270,11 +291,13 @@ static hipError_t rhs_nt(const DNet &n, const double *la, int64_t n_cells, const
   if (k) {
     if (n.layout == LAYOUT_SELL) return rhs_variant<NT, LAYOUT_SELL, true>(n, la, n_cells, y, T, k, dydt, st);
     if (n.layout == LAYOUT_RUNS) return rhs_variant<NT, LAYOUT_RUNS, true>(n, la, n_cells, y, T, k, dydt, st);
+    if (n.layout == LAYOUT_CCS) return rhs_variant<NT, LAYOUT_CCS, true>(n, la, n_cells, y, T, k, dydt, st);
     if (n.layout == LAYOUT_COO) return rhs_variant<NT, LAYOUT_COO, true>(n, la, n_cells, y, T, k, dydt, st);
     return rhs_variant<NT, LAYOUT_CSR, true>(n, la, n_cells, y, T, k, dydt, st);
   }
   if (n.layout == LAYOUT_SELL) return rhs_variant<NT, LAYOUT_SELL, false>(n, la, n_cells, y, T, k, dydt, st);
   if (n.layout == LAYOUT_RUNS) return rhs_variant<NT, LAYOUT_RUNS, false>(n, la, n_cells, y, T, k, dydt, st);
+  if (n.layout == LAYOUT_CCS) return rhs_variant<NT, LAYOUT_CCS, false>(n, la, n_cells, y, T, k, dydt, st);
   if (n.layout == LAYOUT_COO) return rhs_variant<NT, LAYOUT_COO, false>(n, la, n_cells, y, T, k, dydt, st);
   return rhs_variant<NT, LAYOUT_CSR, false>(n, la, n_cells, y, T, k, dydt, st);
 }

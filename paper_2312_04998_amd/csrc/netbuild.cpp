@@ -233,7 +233,7 @@ std::string build_network(int ns, int nr, const int32_t *reactants, const int32_
     return "network larger than AC_MAX_SPECIES / AC_MAX_REACTIONS";
   }
   if (!reactants || !products || !alpha || !beta || !gamma) return "null network array";
-  if (layout < 0 || layout > 3) return "unknown layout";
+  if (layout < 0 || layout > 4) return "unknown layout";
   if (ordering < 0 || ordering > 2) return "unknown ordering";
   if (chunk < 0 || sell_c < 0 || sell_sigma < 0) return "negative chunk/sell parameter";
   chunk = chunk ? chunk : 32;

@@ -57,7 +57,7 @@ def test_rates(acm, torch_dev, oracle_mod, medium_net, med_cells):
     _close(k, ref, 2e-13 / REL * np.abs(ref))
 
 
-@pytest.mark.parametrize("layout", ["csr", "sell", "coo", "runs"])
+@pytest.mark.parametrize("layout", ["csr", "sell", "coo", "runs", "ccs"])
 @pytest.mark.parametrize("ordering", ["natural", "nnz", "rcm"])
 def test_rhs(acm, torch_dev, oracle_mod, medium_net, med_cells, layout, ordering):
     torch = torch_dev
@@ -176,7 +176,7 @@ def test_large_network(acm, torch_dev, oracle_mod):
     cells = synthnet.make_cells(net, 70, synthnet.SEED_BASE + 4)
     y, T = cells.y0, cells.T
     v = np.random.default_rng(1).standard_normal(y.shape)
-    for layout in ("csr", "sell", "runs"):
+    for layout in ("csr", "sell", "runs", "ccs"):
         N = acm.Network.from_synth(net, layout=layout, ordering="rcm")
         f = N.rhs(_t(torch, y), _t(torch, T)).cpu().numpy()
         ref, ab = oracle_mod.rhs(net, y, T, with_abs=True)
@@ -197,7 +197,7 @@ def test_edge_cases(acm, torch_dev, oracle_mod):
     N = acm.Network(net.reactants, net.products, net.alpha, net.beta, net.gamma,
                     composition=np.zeros((3, 6), np.int8))
     y = np.array([[2.0, 7.0, 11.0]])
-    for layout in ("csr", "sell", "coo", "runs"):
+    for layout in ("csr", "sell", "coo", "runs", "ccs"):
         M = acm.Network(net.reactants, net.products, net.alpha, net.beta, net.gamma,
                         composition=np.zeros((3, 6), np.int8), layout=layout)
         f = M.rhs(_t(torch, y), _t(torch, [40.0])).cpu().numpy()

@@ -223,7 +223,7 @@ def test_schedules_cover_every_term(acm, medium_net):
     """Chunking keeps every nonzero of S exactly once (RHS terms), and the
     Jacobian has one term per (entry, reaction, reactant slot)."""
     net = medium_net
-    for layout in ("csr", "sell", "coo", "runs"):
+    for layout in ("csr", "sell", "coo", "runs", "ccs"):
         N = _net(acm, net, layout=layout, chunk=16)
         assert N.n_chunks >= net.n_species
     N = _net(acm, net)
