@@ -270,8 +270,8 @@ def integration_legs(args, torch, acm, net, cells):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(cells shard across GPUs with no communication; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (cells would "
+              "shard across GPUs with no communication).", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
