@@ -151,6 +151,53 @@ __device__ __forceinline__ void runsum_partials(const DSched &s, const double *_
   }
 }
 
+// runsum_partials for two cells at once (densities ys0/ys1, per-reaction
+// values A0/A1, partials part0/part1): the run's mask, slot and items are
+// loaded and decoded once for both.
+template <int NT>
+__device__ __forceinline__ void runsum_partials2(const DSched &s, const double *__restrict__ A0,
+                                                 const double *__restrict__ ys0, double *part0,
+                                                 const double *__restrict__ A1,
+                                                 const double *__restrict__ ys1, double *part1) {
+  for (int t = threadIdx.x; t < s.n_run; t += NT) {
+    const uint32_t mask = s.run_mask[t];
+    int slot = s.run_slot[t];
+    const int len = s.n_item - t * RUN_ITEMS < RUN_ITEMS ? s.n_item - t * RUN_ITEMS : RUN_ITEMS;
+    const uint4 *it4 = s.run_items + size_t(t >> 6) * (RUN_ITEMS / 4) * 64 + (t & 63);
+    uint4 w[RUN_ITEMS / 4];
+#pragma unroll
+    for (int q = 0; q < RUN_ITEMS / 4; ++q) w[q] = it4[q * 64];
+    double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < RUN_ITEMS; ++k) {
+      const uint4 &wq = w[k >> 2];
+      const uint32_t it = (k & 3) == 0 ? wq.x : (k & 3) == 1 ? wq.y : (k & 3) == 2 ? wq.z : wq.w;
+      if (k < len) {
+        if (k > 0 && ((mask >> k) & 1u)) {
+          part0[slot] = acc0;
+          part1[slot] = acc1;
+          ++slot;
+          acc0 = 0.0;
+          acc1 = 0.0;
+        }
+        const int j = int(it & 0xFFFFu), b = int((it >> 16) & 2047u);
+        const double coef = double(int32_t(it) >> 27);
+        double v0 = coef * A0[j], v1 = coef * A1[j];
+        if (b != 2047) {
+          v0 *= ys0[b];
+          v1 *= ys1[b];
+        }
+        acc0 = __dadd_rn(acc0, v0);
+        acc1 = __dadd_rn(acc1, v1);
+      }
+    }
+    if (len > 0) {
+      part0[slot] = acc0;
+      part1[slot] = acc1;
+    }
+  }
+}
+
 // out[seg_out[k]] = sum of segment k's run partials, in order.
 template <int NT, bool STREAM>
 __device__ __forceinline__ void runsum_finish(const DSched &s, const double *part,

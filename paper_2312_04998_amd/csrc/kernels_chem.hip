@@ -149,6 +149,85 @@ __global__ __launch_bounds__(NT) void k_jac(DNet n, const double *__restrict__ l
   }
 }
 
+// The same two tiers for two cells per pass: every network word (reaction
+// record, run, entry descriptor) is loaded and decoded once and serves both
+// cells, which halves the index arithmetic and the L2 reads per cell. Needs
+// twice the LDS, so one 1024-thread workgroup per CU takes the place of two
+// 512-thread ones.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_jac2(DNet n, const double *__restrict__ la_over,
+                                             int64_t n_cells, const double *__restrict__ y,
+                                             const double *__restrict__ T,
+                                             double *__restrict__ jvals) {
+  extern __shared__ double sm[];
+  const int ns = n.ns, nr = n.nr;
+  const int nslot = n.jtail.n_slot > 0 ? n.jtail.n_slot : 1;
+  double *ys0 = sm, *ys1 = ys0 + ns, *ks0 = ys1 + ns, *ks1 = ks0 + nr;
+  double *pt0 = ks1 + nr, *pt1 = pt0 + nslot;
+  for (int64_t c = 2 * int64_t(blockIdx.x); c < n_cells; c += 2 * int64_t(gridDim.x)) {
+    const bool two = c + 1 < n_cells;
+    for (int i = threadIdx.x; i < ns; i += NT) {
+      ys0[i] = y[c * ns + i];
+      ys1[i] = two ? y[(c + 1) * ns + i] : 0.0;
+    }
+    double L0, invT0, L1, invT1;
+    cell_temperature(T[c], L0, invT0);
+    cell_temperature(two ? T[c + 1] : T[c], L1, invT1);
+    for (int j0 = threadIdx.x; j0 < nr; j0 += RXU * NT) {
+      Rx r[RXU];
+#pragma unroll
+      for (int u = 0; u < RXU; ++u) {
+        const int j = j0 + u * NT;
+        if (j < nr) {
+          r[u] = load_rx(n, j);
+          if (la_over) r[u].la = la_over[j];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < RXU; ++u) {
+        const int j = j0 + u * NT;
+        if (j < nr) {
+          ks0[j] = kooij(r[u].la, r[u].beta, r[u].gamma, L0, invT0);
+          ks1[j] = kooij(r[u].la, r[u].beta, r[u].gamma, L1, invT1);
+        }
+      }
+    }
+    __syncthreads();
+    runsum_partials2<NT>(n.jtail, ks0, ys0, pt0, ks1, ys1, pt1);
+    __syncthreads();
+    double *out0 = jvals + c * n.nnz_j, *out1 = out0 + n.nnz_j;
+    constexpr int EU = 4;
+    for (int e0 = threadIdx.x; e0 < n.nnz_j; e0 += EU * NT) {
+      uint32_t h0[EU], h1[EU], td[EU];
+#pragma unroll
+      for (int u = 0; u < EU; ++u) {
+        const int e = e0 + u * NT;
+        const bool ok = e < n.nnz_j;
+        h0[u] = ok ? n.jhead0[e] : PAD_ITEM;
+        h1[u] = ok ? n.jhead1[e] : PAD_ITEM;
+        td[u] = ok ? n.jtaildesc[e] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < EU; ++u) {
+        const int e = e0 + u * NT;
+        if (e < n.nnz_j) {
+          double a0 = term(h0[u], ks0, ys0), a1 = term(h0[u], ks1, ys1);
+          a0 = __dadd_rn(a0, term(h1[u], ks0, ys0));
+          a1 = __dadd_rn(a1, term(h1[u], ks1, ys1));
+          const int q0 = int(td[u] >> 8), nq = int(td[u] & 255u);
+          for (int q = 0; q < nq; ++q) {
+            a0 = __dadd_rn(a0, pt0[q0 + q]);
+            a1 = __dadd_rn(a1, pt1[q0 + q]);
+          }
+          __builtin_nontemporal_store(a0, out0 + e);
+          if (two) __builtin_nontemporal_store(a1, out1 + e);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // -------------------------------------------------------------------- VJP
 //
 // w_j = (S^T v)_j from the packed net column of S; gy_a = sum over reactant
@@ -322,6 +401,13 @@ static hipError_t jac_nt(const DNet &n, const double *la, int64_t n_cells, const
 hipError_t launch_jac(const DNet &n, const double *la, int64_t n_cells, const double *y,
                       const double *T, double *jvals, hipStream_t st) {
   if (n_cells == 0) return hipSuccess;
+  // two cells per pass when their LDS fits one workgroup
+  const size_t lds2 = sizeof(double) * 2 * size_t(n.ns + n.nr + (n.jtail.n_slot > 0 ? n.jtail.n_slot : 1));
+  if (n_cells > 1 && lds2 <= 160 * 1024) {
+    const int g = grid_for(k_jac2<1024>, 1024, lds2, (n_cells + 1) / 2);
+    hipLaunchKernelGGL(k_jac2<1024>, dim3(g), dim3(1024), lds2, st, n, la, n_cells, y, T, jvals);
+    return hipGetLastError();
+  }
 #define CALL(NT) jac_nt<NT>(n, la, n_cells, y, T, jvals, st)
   return AC_DISPATCH_NT(n.block, CALL);
 #undef CALL
