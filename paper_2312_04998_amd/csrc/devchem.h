@@ -210,6 +210,48 @@ __device__ __forceinline__ void runsum_finish(const DSched &s, const double *par
   }
 }
 
+// SELL sums of the rows of S (no density factor) for two cells at once:
+// descriptors and items are loaded and decoded once; per chunk the same
+// left-to-right order as segsum_chunks, so the results are identical.
+// out1 / the second cell may be absent (null).
+template <int NT>
+__device__ __forceinline__ void sell_rows2(const DSched &s, const double *__restrict__ A0,
+                                           const double *__restrict__ A1, double *part0,
+                                           double *part1, double *__restrict__ out0,
+                                           double *__restrict__ out1) {
+  const int npos = s.n_slice * SELL_C;
+  for (int pos = threadIdx.x; pos < npos; pos += NT) {
+    const int sl = pos / SELL_C;
+    const int base = s.slice_ptr[sl];
+    const int width = (s.slice_ptr[sl + 1] - base) / SELL_C;
+    const int len = s.sell_len[pos];
+    const int d = s.sell_dst[pos];
+    const uint32_t *it = s.sell_items + base + (pos - sl * SELL_C);
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int k0 = 0; k0 < width; k0 += UNROLL) {
+      uint32_t v[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) v[u] = (k0 + u < width) ? it[(k0 + u) * SELL_C] : PAD_ITEM;
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u)
+        if (k0 + u < len) {
+          const double coef = double(int32_t(v[u]) >> 27);
+          const int j = int(v[u] & 0xFFFFu);
+          acc0 = fma(coef, A0[j], acc0);
+          acc1 = fma(coef, A1[j], acc1);
+        }
+    }
+    if (d == INT_MIN) continue;
+    if (d >= 0) {
+      out0[d] = acc0;
+      if (out1) out1[d] = acc1;
+    } else {
+      part0[-1 - d] = acc0;
+      part1[-1 - d] = acc1;
+    }
+  }
+}
+
 template <int NT, bool STREAM>
 __device__ __forceinline__ void segsum_finish(const DSched &s, const double *part,
                                               double *__restrict__ out) {

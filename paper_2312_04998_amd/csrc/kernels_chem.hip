@@ -96,6 +96,59 @@ __global__ __launch_bounds__(NT) void k_rhs(DNet n, const double *__restrict__ l
   }
 }
 
+// SELL RHS with fused coefficients for two cells per pass: reaction
+// records and SELL items are loaded and decoded once for both cells (one
+// 1024-thread workgroup per CU holds both cells' LDS). Results are those of
+// k_rhs bit for bit.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_rhs2(DNet n, const double *__restrict__ la_over,
+                                             int64_t n_cells, const double *__restrict__ y,
+                                             const double *__restrict__ T,
+                                             double *__restrict__ dydt) {
+  extern __shared__ double sm[];
+  const int ns = n.ns, nr = n.nr;
+  const int nslot = n.rhs.n_slot > 0 ? n.rhs.n_slot : 1;
+  double *ys0 = sm, *ys1 = ys0 + ns, *rs0 = ys1 + ns, *rs1 = rs0 + nr;
+  double *pt0 = rs1 + nr, *pt1 = pt0 + nslot;
+  for (int64_t c = 2 * int64_t(blockIdx.x); c < n_cells; c += 2 * int64_t(gridDim.x)) {
+    const bool two = c + 1 < n_cells;
+    for (int i = threadIdx.x; i < ns; i += NT) {
+      ys0[i] = y[c * ns + i];
+      ys1[i] = two ? y[(c + 1) * ns + i] : 0.0;
+    }
+    double L0, invT0, L1, invT1;
+    cell_temperature(T[c], L0, invT0);
+    cell_temperature(two ? T[c + 1] : T[c], L1, invT1);
+    __syncthreads();
+    for (int j0 = threadIdx.x; j0 < nr; j0 += RXU * NT) {
+      Rx r[RXU];
+#pragma unroll
+      for (int u = 0; u < RXU; ++u) {
+        const int j = j0 + u * NT;
+        if (j < nr) {
+          r[u] = load_rx(n, j);
+          if (la_over) r[u].la = la_over[j];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < RXU; ++u) {
+        const int j = j0 + u * NT;
+        if (j < nr) {
+          rs0[j] = reaction_rate(r[u].pair, kooij(r[u].la, r[u].beta, r[u].gamma, L0, invT0), ys0);
+          rs1[j] = reaction_rate(r[u].pair, kooij(r[u].la, r[u].beta, r[u].gamma, L1, invT1), ys1);
+        }
+      }
+    }
+    __syncthreads();
+    double *out0 = dydt + c * ns, *out1 = two ? out0 + ns : nullptr;
+    sell_rows2<NT>(n.rhs, rs0, rs1, pt0, pt1, out0, out1);
+    __syncthreads();
+    segsum_finish<NT, false>(n.rhs, pt0, out0);
+    if (two) segsum_finish<NT, false>(n.rhs, pt1, out1);
+    __syncthreads();
+  }
+}
+
 // --------------------------------------------------------------- Jacobian
 //
 // Two tiers: the tails (terms beyond the second of an entry; a few
@@ -384,6 +437,13 @@ static hipError_t rhs_nt(const DNet &n, const double *la, int64_t n_cells, const
 hipError_t launch_rhs(const DNet &n, const double *la, int64_t n_cells, const double *y,
                       const double *T, const double *k, double *dydt, hipStream_t st) {
   if (n_cells == 0) return hipSuccess;
+  // SELL with fused coefficients: two cells per pass when their LDS fits
+  const size_t lds2 = sizeof(double) * 2 * size_t(n.ns + n.nr + (n.rhs.n_slot > 0 ? n.rhs.n_slot : 1));
+  if (!k && n.layout == LAYOUT_SELL && n_cells > 1 && lds2 <= 160 * 1024) {
+    const int g = grid_for(k_rhs2<1024>, 1024, lds2, (n_cells + 1) / 2);
+    hipLaunchKernelGGL(k_rhs2<1024>, dim3(g), dim3(1024), lds2, st, n, la, n_cells, y, T, dydt);
+    return hipGetLastError();
+  }
 #define CALL(NT) rhs_nt<NT>(n, la, n_cells, y, T, k, dydt, st)
   return AC_DISPATCH_NT(n.block, CALL);
 #undef CALL
