@@ -88,16 +88,22 @@ def cpu_baseline(net, cells, seconds):
     oracle.jac_dense(net, cells.y0[:probe], cells.T[:probe])
     dt = max(time.perf_counter() - t0, 1e-6)
     n = int(min(cells.T.size, max(probe, probe * seconds / dt)))
+    # whole passes over the sample until about `seconds` have elapsed
     t0 = time.perf_counter()
-    for s in range(0, n, 256):
-        e = min(n, s + 256)
-        oracle.rhs(net, cells.y0[s:e], cells.T[s:e])
-        oracle.jac_dense(net, cells.y0[s:e], cells.T[s:e])
-    dt = time.perf_counter() - t0
-    return {"value": n * net.n_reactions / dt, "unit": "cell-reactions/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"RHS + dense Jacobian of the first {n} of the {cells.T.size} cells "
-                      f"({dt:.1f} s, {threads} threads)"}
+    passes = 0
+    while True:
+        for s in range(0, n, 256):
+            e = min(n, s + 256)
+            oracle.rhs(net, cells.y0[s:e], cells.T[s:e])
+            oracle.jac_dense(net, cells.y0[s:e], cells.T[s:e])
+        passes += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds or n < cells.T.size:
+            break
+    return {"value": passes * n * net.n_reactions / dt, "unit": "cell-reactions/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"RHS + dense Jacobian of the first {n} of the {cells.T.size} cells, "
+                      f"{passes} pass(es) in {dt:.1f} s on {threads} threads"}
 
 
 # Sources that make up the Jacobian kernel: the HBM traffic recorded under
