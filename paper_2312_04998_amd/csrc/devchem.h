@@ -151,14 +151,28 @@ __device__ __forceinline__ void runsum_partials(const DSched &s, const double *_
   }
 }
 
-// runsum_partials for two cells at once (densities ys0/ys1, per-reaction
-// values A0/A1, partials part0/part1): the run's mask, slot and items are
-// loaded and decoded once for both.
+// One packed term for two cells whose values sit side by side in LDS:
+// A2[j] = (A_j of cell 0, A_j of cell 1), y2[b] likewise, where y2[ynone]
+// holds (1, 1) and stands for "no density factor" (b = NONE is clamped to
+// ynone, every real species index is below it). acc += coef * (A_j y_b).
+__device__ __forceinline__ void term_pair(uint32_t it, const double2 *__restrict__ A2,
+                                          const double2 *__restrict__ y2, uint32_t ynone,
+                                          double &acc0, double &acc1) {
+  const uint32_t b = min((it >> 16) & 2047u, ynone);
+  const double coef = double(int32_t(it) >> 27);
+  const double2 kv = A2[it & 0xFFFFu], yv = y2[b];
+  acc0 = fma(coef, kv.x * yv.x, acc0);
+  acc1 = fma(coef, kv.y * yv.y, acc1);
+}
+
+// runsum_partials for two cells at once, over interleaved per-reaction
+// values A2 and densities y2 (see term_pair); the partials of both cells
+// go to part2[slot] as one pair. The run's mask, slot and items are loaded
+// and decoded once for both cells, and every LDS access serves both.
 template <int NT>
-__device__ __forceinline__ void runsum_partials2(const DSched &s, const double *__restrict__ A0,
-                                                 const double *__restrict__ ys0, double *part0,
-                                                 const double *__restrict__ A1,
-                                                 const double *__restrict__ ys1, double *part1) {
+__device__ __forceinline__ void runsum_pairs(const DSched &s, const double2 *__restrict__ A2,
+                                             const double2 *__restrict__ y2, uint32_t ynone,
+                                             double2 *part2) {
   for (int t = threadIdx.x; t < s.n_run; t += NT) {
     const uint32_t mask = s.run_mask[t];
     int slot = s.run_slot[t];
@@ -174,27 +188,14 @@ __device__ __forceinline__ void runsum_partials2(const DSched &s, const double *
       const uint32_t it = (k & 3) == 0 ? wq.x : (k & 3) == 1 ? wq.y : (k & 3) == 2 ? wq.z : wq.w;
       if (k < len) {
         if (k > 0 && ((mask >> k) & 1u)) {
-          part0[slot] = acc0;
-          part1[slot] = acc1;
-          ++slot;
+          part2[slot++] = make_double2(acc0, acc1);
           acc0 = 0.0;
           acc1 = 0.0;
         }
-        const int j = int(it & 0xFFFFu), b = int((it >> 16) & 2047u);
-        const double coef = double(int32_t(it) >> 27);
-        double v0 = coef * A0[j], v1 = coef * A1[j];
-        if (b != 2047) {
-          v0 *= ys0[b];
-          v1 *= ys1[b];
-        }
-        acc0 = __dadd_rn(acc0, v0);
-        acc1 = __dadd_rn(acc1, v1);
+        term_pair(it, A2, y2, ynone, acc0, acc1);
       }
     }
-    if (len > 0) {
-      part0[slot] = acc0;
-      part1[slot] = acc1;
-    }
+    if (len > 0) part2[slot] = make_double2(acc0, acc1);
   }
 }
 
@@ -210,14 +211,15 @@ __device__ __forceinline__ void runsum_finish(const DSched &s, const double *par
   }
 }
 
-// SELL sums of the rows of S (no density factor) for two cells at once:
-// descriptors and items are loaded and decoded once; per chunk the same
-// left-to-right order as segsum_chunks, so the results are identical.
-// out1 / the second cell may be absent (null).
+// SELL sums of the rows of S (no density factor) for two cells at once,
+// over interleaved per-reaction values A2[j] = (cell 0, cell 1):
+// descriptors and items are loaded and decoded once and one LDS access
+// serves both cells; per chunk the same left-to-right order as
+// segsum_chunks, so the results are identical. Split segments leave pairs
+// of partials in part2. out1 / the second cell may be absent (null).
 template <int NT>
-__device__ __forceinline__ void sell_rows2(const DSched &s, const double *__restrict__ A0,
-                                           const double *__restrict__ A1, double *part0,
-                                           double *part1, double *__restrict__ out0,
+__device__ __forceinline__ void sell_pairs(const DSched &s, const double2 *__restrict__ A2,
+                                           double2 *part2, double *__restrict__ out0,
                                            double *__restrict__ out1) {
   const int npos = s.n_slice * SELL_C;
   for (int pos = threadIdx.x; pos < npos; pos += NT) {
@@ -236,9 +238,9 @@ __device__ __forceinline__ void sell_rows2(const DSched &s, const double *__rest
       for (int u = 0; u < UNROLL; ++u)
         if (k0 + u < len) {
           const double coef = double(int32_t(v[u]) >> 27);
-          const int j = int(v[u] & 0xFFFFu);
-          acc0 = fma(coef, A0[j], acc0);
-          acc1 = fma(coef, A1[j], acc1);
+          const double2 a = A2[v[u] & 0xFFFFu];
+          acc0 = fma(coef, a.x, acc0);
+          acc1 = fma(coef, a.y, acc1);
         }
     }
     if (d == INT_MIN) continue;
@@ -246,9 +248,26 @@ __device__ __forceinline__ void sell_rows2(const DSched &s, const double *__rest
       out0[d] = acc0;
       if (out1) out1[d] = acc1;
     } else {
-      part0[-1 - d] = acc0;
-      part1[-1 - d] = acc1;
+      part2[-1 - d] = make_double2(acc0, acc1);
     }
+  }
+}
+
+// segsum_finish for pairs of partials (out1 may be null).
+template <int NT>
+__device__ __forceinline__ void segsum_finish_pairs(const DSched &s, const double2 *part2,
+                                                    double *__restrict__ out0,
+                                                    double *__restrict__ out1) {
+  for (int m = threadIdx.x; m < s.n_multi; m += NT) {
+    const int q0 = s.multi_slot[m], q1 = s.multi_slot[m + 1];
+    double2 acc = part2[q0];
+    for (int q = q0 + 1; q < q1; ++q) {
+      const double2 p = part2[q];
+      acc.x = __dadd_rn(acc.x, p.x);
+      acc.y = __dadd_rn(acc.y, p.y);
+    }
+    out0[s.multi_out[m]] = acc.x;
+    if (out1) out1[s.multi_out[m]] = acc.y;
   }
 }
 

@@ -97,9 +97,10 @@ __global__ __launch_bounds__(NT) void k_rhs(DNet n, const double *__restrict__ l
 }
 
 // SELL RHS with fused coefficients for two cells per pass: reaction
-// records and SELL items are loaded and decoded once for both cells (one
-// 1024-thread workgroup per CU holds both cells' LDS). Results are those of
-// k_rhs bit for bit.
+// records and SELL items are loaded and decoded once for both cells, whose
+// densities, rates and partials sit side by side in LDS (16-byte pairs), so
+// one LDS access serves both (one 1024-thread workgroup per CU holds both
+// cells' LDS). Results are those of k_rhs bit for bit.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_rhs2(DNet n, const double *__restrict__ la_over,
                                              int64_t n_cells, const double *__restrict__ y,
@@ -107,15 +108,13 @@ __global__ __launch_bounds__(NT) void k_rhs2(DNet n, const double *__restrict__ 
                                              double *__restrict__ dydt) {
   extern __shared__ double sm[];
   const int ns = n.ns, nr = n.nr;
-  const int nslot = n.rhs.n_slot > 0 ? n.rhs.n_slot : 1;
-  double *ys0 = sm, *ys1 = ys0 + ns, *rs0 = ys1 + ns, *rs1 = rs0 + nr;
-  double *pt0 = rs1 + nr, *pt1 = pt0 + nslot;
+  double2 *yy = reinterpret_cast<double2 *>(sm);   // ns
+  double2 *rr = yy + ns;                             // nr
+  double2 *pp = rr + nr;                             // n_slot
   for (int64_t c = 2 * int64_t(blockIdx.x); c < n_cells; c += 2 * int64_t(gridDim.x)) {
     const bool two = c + 1 < n_cells;
-    for (int i = threadIdx.x; i < ns; i += NT) {
-      ys0[i] = y[c * ns + i];
-      ys1[i] = two ? y[(c + 1) * ns + i] : 0.0;
-    }
+    for (int i = threadIdx.x; i < ns; i += NT)
+      yy[i] = make_double2(y[c * ns + i], two ? y[(c + 1) * ns + i] : 0.0);
     double L0, invT0, L1, invT1;
     cell_temperature(T[c], L0, invT0);
     cell_temperature(two ? T[c + 1] : T[c], L1, invT1);
@@ -134,17 +133,24 @@ __global__ __launch_bounds__(NT) void k_rhs2(DNet n, const double *__restrict__ 
       for (int u = 0; u < RXU; ++u) {
         const int j = j0 + u * NT;
         if (j < nr) {
-          rs0[j] = reaction_rate(r[u].pair, kooij(r[u].la, r[u].beta, r[u].gamma, L0, invT0), ys0);
-          rs1[j] = reaction_rate(r[u].pair, kooij(r[u].la, r[u].beta, r[u].gamma, L1, invT1), ys1);
+          const double2 ya = yy[r[u].pair & 0xFFFFu];
+          double r0 = kooij(r[u].la, r[u].beta, r[u].gamma, L0, invT0) * ya.x;
+          double r1 = kooij(r[u].la, r[u].beta, r[u].gamma, L1, invT1) * ya.y;
+          const uint32_t b = r[u].pair >> 16;
+          if (b != 0xFFFFu) {
+            const double2 yb = yy[b];
+            r0 *= yb.x;
+            r1 *= yb.y;
+          }
+          rr[j] = make_double2(r0, r1);
         }
       }
     }
     __syncthreads();
     double *out0 = dydt + c * ns, *out1 = two ? out0 + ns : nullptr;
-    sell_rows2<NT>(n.rhs, rs0, rs1, pt0, pt1, out0, out1);
+    sell_pairs<NT>(n.rhs, rr, pp, out0, out1);
     __syncthreads();
-    segsum_finish<NT, false>(n.rhs, pt0, out0);
-    if (two) segsum_finish<NT, false>(n.rhs, pt1, out1);
+    segsum_finish_pairs<NT>(n.rhs, pp, out0, out1);
     __syncthreads();
   }
 }
@@ -204,7 +210,12 @@ __global__ __launch_bounds__(NT) void k_jac(DNet n, const double *__restrict__ l
 
 // The same two tiers for two cells per pass: every network word (reaction
 // record, run, entry descriptor) is loaded and decoded once and serves both
-// cells, which halves the index arithmetic and the L2 reads per cell. Needs
+// cells. The two cells' values sit side by side in LDS (a 16-byte pair per
+// species, reaction and tail slot), so one LDS access and one address serve
+// both cells. The species pair after the last holds (1, 1) for terms
+// without a density factor and the slot pair after the last holds (0, 0),
+// so every entry reads its two head terms and its first two tail slots
+// without branching; only the few entries with more tail slots loop. Needs
 // twice the LDS, so one 1024-thread workgroup per CU takes the place of two
 // 512-thread ones.
 template <int NT>
@@ -213,16 +224,19 @@ __global__ __launch_bounds__(NT) void k_jac2(DNet n, const double *__restrict__ 
                                              const double *__restrict__ T,
                                              double *__restrict__ jvals) {
   extern __shared__ double sm[];
-  const int ns = n.ns, nr = n.nr;
-  const int nslot = n.jtail.n_slot > 0 ? n.jtail.n_slot : 1;
-  double *ys0 = sm, *ys1 = ys0 + ns, *ks0 = ys1 + ns, *ks1 = ks0 + nr;
-  double *pt0 = ks1 + nr, *pt1 = pt0 + nslot;
+  const int ns = n.ns, nr = n.nr, nnz = n.nnz_j;
+  const uint32_t nslot = uint32_t(n.jtail.n_slot > 0 ? n.jtail.n_slot : 0);
+  double2 *yy = reinterpret_cast<double2 *>(sm);   // ns + 1
+  double2 *kk = yy + ns + 1;                         // nr
+  double2 *pp = kk + nr;                             // nslot + 1
+  if (threadIdx.x == 0) {
+    yy[ns] = make_double2(1.0, 1.0);
+    pp[nslot] = make_double2(0.0, 0.0);
+  }
   for (int64_t c = 2 * int64_t(blockIdx.x); c < n_cells; c += 2 * int64_t(gridDim.x)) {
     const bool two = c + 1 < n_cells;
-    for (int i = threadIdx.x; i < ns; i += NT) {
-      ys0[i] = y[c * ns + i];
-      ys1[i] = two ? y[(c + 1) * ns + i] : 0.0;
-    }
+    for (int i = threadIdx.x; i < ns; i += NT)
+      yy[i] = make_double2(y[c * ns + i], two ? y[(c + 1) * ns + i] : 0.0);
     double L0, invT0, L1, invT1;
     cell_temperature(T[c], L0, invT0);
     cell_temperature(two ? T[c + 1] : T[c], L1, invT1);
@@ -239,38 +253,42 @@ __global__ __launch_bounds__(NT) void k_jac2(DNet n, const double *__restrict__ 
 #pragma unroll
       for (int u = 0; u < RXU; ++u) {
         const int j = j0 + u * NT;
-        if (j < nr) {
-          ks0[j] = kooij(r[u].la, r[u].beta, r[u].gamma, L0, invT0);
-          ks1[j] = kooij(r[u].la, r[u].beta, r[u].gamma, L1, invT1);
-        }
+        if (j < nr)
+          kk[j] = make_double2(kooij(r[u].la, r[u].beta, r[u].gamma, L0, invT0),
+                               kooij(r[u].la, r[u].beta, r[u].gamma, L1, invT1));
       }
     }
     __syncthreads();
-    runsum_partials2<NT>(n.jtail, ks0, ys0, pt0, ks1, ys1, pt1);
+    runsum_pairs<NT>(n.jtail, kk, yy, uint32_t(ns), pp);
     __syncthreads();
-    double *out0 = jvals + c * n.nnz_j, *out1 = out0 + n.nnz_j;
+    double *out0 = jvals + c * nnz, *out1 = out0 + nnz;
+    const uint32_t unnz = uint32_t(nnz);
     constexpr int EU = 4;
-    for (int e0 = threadIdx.x; e0 < n.nnz_j; e0 += EU * NT) {
+    for (uint32_t e0 = threadIdx.x; e0 < unnz; e0 += EU * NT) {
       uint32_t h0[EU], h1[EU], td[EU];
 #pragma unroll
       for (int u = 0; u < EU; ++u) {
-        const int e = e0 + u * NT;
-        const bool ok = e < n.nnz_j;
+        const uint32_t e = e0 + u * NT;
+        const bool ok = e < unnz;
         h0[u] = ok ? n.jhead0[e] : PAD_ITEM;
         h1[u] = ok ? n.jhead1[e] : PAD_ITEM;
         td[u] = ok ? n.jtaildesc[e] : 0u;
       }
 #pragma unroll
       for (int u = 0; u < EU; ++u) {
-        const int e = e0 + u * NT;
-        if (e < n.nnz_j) {
-          double a0 = term(h0[u], ks0, ys0), a1 = term(h0[u], ks1, ys1);
-          a0 = __dadd_rn(a0, term(h1[u], ks0, ys0));
-          a1 = __dadd_rn(a1, term(h1[u], ks1, ys1));
-          const int q0 = int(td[u] >> 8), nq = int(td[u] & 255u);
-          for (int q = 0; q < nq; ++q) {
-            a0 = __dadd_rn(a0, pt0[q0 + q]);
-            a1 = __dadd_rn(a1, pt1[q0 + q]);
+        const uint32_t e = e0 + u * NT;
+        if (e < unnz) {
+          double a0 = 0.0, a1 = 0.0;
+          term_pair(h0[u], kk, yy, uint32_t(ns), a0, a1);
+          term_pair(h1[u], kk, yy, uint32_t(ns), a0, a1);
+          const uint32_t q0 = td[u] >> 8, nq = td[u] & 255u;
+          const double2 p0 = pp[nq > 0u ? q0 : nslot], p1 = pp[nq > 1u ? q0 + 1u : nslot];
+          a0 = __dadd_rn(__dadd_rn(a0, p0.x), p1.x);
+          a1 = __dadd_rn(__dadd_rn(a1, p0.y), p1.y);
+          for (uint32_t q = 2; q < nq; ++q) {
+            const double2 pq = pp[q0 + q];
+            a0 = __dadd_rn(a0, pq.x);
+            a1 = __dadd_rn(a1, pq.y);
           }
           __builtin_nontemporal_store(a0, out0 + e);
           if (two) __builtin_nontemporal_store(a1, out1 + e);
@@ -438,7 +456,7 @@ hipError_t launch_rhs(const DNet &n, const double *la, int64_t n_cells, const do
                       const double *T, const double *k, double *dydt, hipStream_t st) {
   if (n_cells == 0) return hipSuccess;
   // SELL with fused coefficients: two cells per pass when their LDS fits
-  const size_t lds2 = sizeof(double) * 2 * size_t(n.ns + n.nr + (n.rhs.n_slot > 0 ? n.rhs.n_slot : 1));
+  const size_t lds2 = 2 * sizeof(double) * size_t(n.ns + n.nr + (n.rhs.n_slot > 0 ? n.rhs.n_slot : 1));
   if (!k && n.layout == LAYOUT_SELL && n_cells > 1 && lds2 <= 160 * 1024) {
     const int g = grid_for(k_rhs2<1024>, 1024, lds2, (n_cells + 1) / 2);
     hipLaunchKernelGGL(k_rhs2<1024>, dim3(g), dim3(1024), lds2, st, n, la, n_cells, y, T, dydt);
@@ -462,7 +480,9 @@ hipError_t launch_jac(const DNet &n, const double *la, int64_t n_cells, const do
                       const double *T, double *jvals, hipStream_t st) {
   if (n_cells == 0) return hipSuccess;
   // two cells per pass when their LDS fits one workgroup
-  const size_t lds2 = sizeof(double) * 2 * size_t(n.ns + n.nr + (n.jtail.n_slot > 0 ? n.jtail.n_slot : 1));
+  // pairs of doubles: species + (1, 1), reactions, tail slots + (0, 0)
+  const size_t lds2 = 2 * sizeof(double) *
+                      size_t(n.ns + 1 + n.nr + (n.jtail.n_slot > 0 ? n.jtail.n_slot : 0) + 1);
   if (n_cells > 1 && lds2 <= 160 * 1024) {
     const int g = grid_for(k_jac2<1024>, 1024, lds2, (n_cells + 1) / 2);
     hipLaunchKernelGGL(k_jac2<1024>, dim3(g), dim3(1024), lds2, st, n, la, n_cells, y, T, jvals);
