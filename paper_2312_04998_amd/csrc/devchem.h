@@ -211,14 +211,17 @@ __device__ __forceinline__ void runsum_finish(const DSched &s, const double *par
   }
 }
 
-// SELL sums of the rows of S (no density factor) for two cells at once,
-// over interleaved per-reaction values A2[j] = (cell 0, cell 1):
-// descriptors and items are loaded and decoded once and one LDS access
-// serves both cells; per chunk the same left-to-right order as
-// segsum_chunks, so the results are identical. Split segments leave pairs
-// of partials in part2. out1 / the second cell may be absent (null).
-template <int NT>
+// SELL sums for two cells at once, over interleaved per-reaction values
+// A2[j] = (cell 0, cell 1): descriptors and items are loaded and decoded
+// once and one LDS access serves both cells. Without a density factor
+// (HASB = false: the rows of S) each chunk takes the same left-to-right
+// fused multiply-adds as segsum_chunks, so the results are identical; with
+// one, terms are term_pair's over the interleaved densities y2 (y2[ynone]
+// = (1, 1)). Split segments leave pairs of partials in part2. out1 / the
+// second cell may be absent (null).
+template <int NT, bool HASB = false>
 __device__ __forceinline__ void sell_pairs(const DSched &s, const double2 *__restrict__ A2,
+                                           const double2 *__restrict__ y2, uint32_t ynone,
                                            double2 *part2, double *__restrict__ out0,
                                            double *__restrict__ out1) {
   const int npos = s.n_slice * SELL_C;
@@ -237,10 +240,14 @@ __device__ __forceinline__ void sell_pairs(const DSched &s, const double2 *__res
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u)
         if (k0 + u < len) {
-          const double coef = double(int32_t(v[u]) >> 27);
-          const double2 a = A2[v[u] & 0xFFFFu];
-          acc0 = fma(coef, a.x, acc0);
-          acc1 = fma(coef, a.y, acc1);
+          if (HASB) {
+            term_pair(v[u], A2, y2, ynone, acc0, acc1);
+          } else {
+            const double coef = double(int32_t(v[u]) >> 27);
+            const double2 a = A2[v[u] & 0xFFFFu];
+            acc0 = fma(coef, a.x, acc0);
+            acc1 = fma(coef, a.y, acc1);
+          }
         }
     }
     if (d == INT_MIN) continue;

@@ -148,7 +148,7 @@ __global__ __launch_bounds__(NT) void k_rhs2(DNet n, const double *__restrict__ 
     }
     __syncthreads();
     double *out0 = dydt + c * ns, *out1 = two ? out0 + ns : nullptr;
-    sell_pairs<NT>(n.rhs, rr, pp, out0, out1);
+    sell_pairs<NT>(n.rhs, rr, nullptr, 0u, pp, out0, out1);
     __syncthreads();
     segsum_finish_pairs<NT>(n.rhs, pp, out0, out1);
     __syncthreads();
@@ -356,6 +356,95 @@ __global__ __launch_bounds__(NT) void k_vjp(DNet n, const double *__restrict__ l
   }
 }
 
+// The VJP for two cells per pass, their values side by side in LDS (16-byte
+// pairs; the species pair after the last holds (1, 1) for terms without a
+// density factor): each packed column of S and each gy item is decoded once
+// for both cells, and one LDS access serves both. The log-alpha partial row
+// of a workgroup adds the first cell's term, then the second's.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_vjp2(DNet n, const double *__restrict__ la_over,
+                                             int64_t n_cells, const double *__restrict__ y,
+                                             const double *__restrict__ T,
+                                             const double *__restrict__ v,
+                                             double *__restrict__ gy,
+                                             double *__restrict__ part_glog) {
+  extern __shared__ double sm[];
+  const int ns = n.ns, nr = n.nr;
+  double2 *yy = reinterpret_cast<double2 *>(sm);   // ns + 1
+  double2 *vv = yy + ns + 1;                         // ns
+  double2 *kw = vv + ns;                             // nr
+  double2 *pp = kw + nr;                             // gy slots
+  double *prow = part_glog ? part_glog + size_t(blockIdx.x) * nr : nullptr;
+  if (prow)
+    for (int j = threadIdx.x; j < nr; j += NT) prow[j] = 0.0;
+  if (threadIdx.x == 0) yy[ns] = make_double2(1.0, 1.0);
+  for (int64_t c = 2 * int64_t(blockIdx.x); c < n_cells; c += 2 * int64_t(gridDim.x)) {
+    const bool two = c + 1 < n_cells;
+    for (int i = threadIdx.x; i < ns; i += NT) {
+      yy[i] = make_double2(y[c * ns + i], two ? y[(c + 1) * ns + i] : 0.0);
+      vv[i] = make_double2(v[c * ns + i], two ? v[(c + 1) * ns + i] : 0.0);
+    }
+    double L0, invT0, L1, invT1;
+    cell_temperature(T[c], L0, invT0);
+    cell_temperature(two ? T[c + 1] : T[c], L1, invT1);
+    __syncthreads();
+    for (int j0 = threadIdx.x; j0 < nr; j0 += RXU * NT) {
+      Rx r[RXU];
+      uint4 col[RXU];
+#pragma unroll
+      for (int u = 0; u < RXU; ++u) {
+        const int j = j0 + u * NT;
+        if (j < nr) {
+          r[u] = load_rx(n, j);
+          col[u] = n.rxpack[2 * nr + j];
+          if (la_over) r[u].la = la_over[j];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < RXU; ++u) {
+        const int j = j0 + u * NT;
+        if (j >= nr) continue;
+        const uint32_t w4[4] = {col[u].x, col[u].y, col[u].z, col[u].w};
+        double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const uint32_t h = (w4[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+          if (h != 0xFFFFu) {
+            const double coef = double(int32_t(h << 16) >> 27);
+            const double2 vq = vv[h & 2047u];
+            w0 += coef * vq.x;
+            w1 += coef * vq.y;
+          }
+        }
+        const double k0 = kooij(r[u].la, r[u].beta, r[u].gamma, L0, invT0);
+        const double k1 = kooij(r[u].la, r[u].beta, r[u].gamma, L1, invT1);
+        kw[j] = make_double2(k0 * w0, k1 * w1);
+        if (prow) {
+          const uint32_t pair = r[u].pair;
+          const double2 ya = yy[pair & 0xFFFFu];
+          double r0 = k0 * ya.x, r1 = k1 * ya.y;
+          if ((pair >> 16) != 0xFFFFu) {
+            const double2 yb = yy[pair >> 16];
+            r0 *= yb.x;
+            r1 *= yb.y;
+          }
+          double g = prow[j] + r0 * w0;
+          if (two) g += r1 * w1;
+          prow[j] = g;
+        }
+      }
+    }
+    __syncthreads();
+    if (gy) {
+      double *out0 = gy + c * ns, *out1 = two ? out0 + ns : nullptr;
+      sell_pairs<NT, true>(n.gy, kw, yy, uint32_t(ns), pp, out0, out1);
+      __syncthreads();
+      segsum_finish_pairs<NT>(n.gy, pp, out0, out1);
+    }
+    __syncthreads();
+  }
+}
+
 constexpr int RED_NT = 256;
 
 __global__ __launch_bounds__(RED_NT) void k_fill(double *__restrict__ p, int64_t n, double v) {
@@ -533,6 +622,24 @@ hipError_t launch_vjp(const DNet &n, const double *la, int64_t n_cells, const do
       return hipGetLastError();
     }
     return hipSuccess;
+  }
+  // pairs of doubles: species + (1, 1), v, reactions, gy slots
+  const size_t lds2 = 2 * sizeof(double) *
+                      size_t(2 * n.ns + 1 + n.nr + (n.gy.n_slot > 0 ? n.gy.n_slot : 1));
+  if (n_cells > 1 && lds2 <= 160 * 1024 && part_rows >= 2) {
+    // fixed grid, as in vjp_nt: at most half the partial rows, one
+    // workgroup per CU at this LDS size
+    const int64_t pairs = (n_cells + 1) / 2;
+    const int g = int(pairs < part_rows / 2 ? pairs : part_rows / 2);
+    hipFuncSetAttribute(reinterpret_cast<const void *>(k_vjp2<1024>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds2));
+    hipLaunchKernelGGL(k_vjp2<1024>, dim3(g), dim3(1024), lds2, st, n, la, n_cells, y, T, v, gy,
+                       g_logalpha ? part : nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !g_logalpha) return e;
+    hipLaunchKernelGGL(k_sum_rows, dim3((n.nr + RED_NT - 1) / RED_NT), dim3(RED_NT), 0, st, part,
+                       g, n.nr, g_logalpha);
+    return hipGetLastError();
   }
 #define CALL(NT) vjp_nt<NT>(n, la, n_cells, y, T, v, gy, g_logalpha, part, part_rows, st)
   return AC_DISPATCH_NT(n.block, CALL);
