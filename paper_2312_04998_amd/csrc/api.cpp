@@ -414,7 +414,7 @@ ac_status ac_lu_solve(int32_t n, int32_t lda, int64_t n_mat, const double *LU,
                       const int32_t *piv, double *b, int32_t trans, ac_stream stream) {
   if (n <= 0 || lda < n || n_mat < 0) return fail(AC_EINVAL, "need n > 0, lda >= n, n_mat >= 0");
   if (n_mat && (!LU || !piv || !b)) return fail(AC_EINVAL, "null LU, piv or b");
-  if (sizeof(double) * (size_t(2) * n + ac::SB * ac::SBP) + sizeof(int) * size_t(n) > 160 * 1024)
+  if (sizeof(double) * (size_t(2) * n + 2 * ac::SB * ac::SBP) + sizeof(int) * size_t(n) > 160 * 1024)
     return fail(AC_ELIMIT, "n too large for an LDS-resident right-hand side");
   hipError_t e = ac::launch_lu_solve(n, lda, n_mat, LU, piv, b, trans, hipStream_t(stream));
   return e == hipSuccess ? AC_OK : hip_fail(e, "ac_lu_solve launch");

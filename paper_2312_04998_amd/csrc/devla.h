@@ -24,7 +24,7 @@ constexpr int SBP = SB + 1;   // its LDS row stride (odd: row-wise lane reads av
 // LDS the factorisation / solves need besides the right-hand side (doubles).
 __host__ __device__ inline int la_scratch_doubles(int n) {
   const int pan = n * PW + PW * PW;
-  const int blk = SB * SBP;
+  const int blk = 2 * SB * SBP;   // the solves' two staged diagonal blocks
   return pan > blk ? pan : blk;
 }
 
@@ -409,35 +409,40 @@ __device__ __forceinline__ int wg_lu(double *__restrict__ A, int lda, int n, int
 // staged in LDS (row stride SBP, zero beyond bs) and solved by the first
 // wavefront (lane = row). In the chains below each step's operand comes
 // from registers loaded 16 at a time, and the lane holding the newest
-// unknown hands it to the others through a scalar register.
-template <int NT>
-__device__ __forceinline__ void stage_block(const double *LU, int lda, int b0, int bs, double *blk) {
-  constexpr int U = (SB * SB) / NT;   // every load of the block in flight at once
+// unknown hands it to the others through a scalar register. stage_block
+// runs on NTH threads, t = 0 .. NTH-1 being the caller's index among them.
+template <int NTH>
+__device__ __forceinline__ void stage_block(const double *LU, int lda, int b0, int bs, double *blk,
+                                            int t) {
+  constexpr int U = (SB * SB + NTH - 1) / NTH;   // every load of the block in flight at once
   double v[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int e = threadIdx.x + u * NT, r = e / SB, q = e - r * SB;
-    v[u] = (r < bs && q < bs) ? LU[size_t(b0 + r) * lda + b0 + q] : 0.0;
+    const int e = t + u * NTH, r = e / SB, q = e - r * SB;
+    v[u] = (e < SB * SB && r < bs && q < bs) ? LU[size_t(b0 + r) * lda + b0 + q] : 0.0;
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int e = threadIdx.x + u * NT, r = e / SB, q = e - r * SB;
-    blk[r * SBP + q] = v[u];
+    const int e = t + u * NTH, r = e / SB, q = e - r * SB;
+    if (e < SB * SB) blk[r * SBP + q] = v[u];
   }
 }
 
 // out[i] -= sum_{q < bs} M(i, q) x[b0 + q] with M(i, q) = rowmajor ?
-// LU[i][b0+q] : LU[b0+q][i], for i in [i0, i1). Row-major: four lanes
-// share a row (interleaved columns, so a quad reads 32 contiguous bytes),
-// reduced with shuffles. Column-major: one lane per row, so a wave reads
-// contiguous rows. All 16 loads of a lane are in flight together.
-template <int NT, bool ROWMAJOR>
+// LU[i][b0+q] : LU[b0+q][i], for i in [i0, i1), on NTH threads (t as in
+// stage_block; NTH a multiple of 4, t = threadIdx.x - a multiple of 64).
+// Row-major: four lanes share a row (interleaved columns, so a quad reads
+// 32 contiguous bytes), reduced with shuffles. Column-major: one lane per
+// row, so a wave reads contiguous rows. All 16 loads of a lane are in
+// flight together. A row's sum depends only on its data, not on which
+// threads form it.
+template <int NTH, bool ROWMAJOR>
 __device__ __forceinline__ void block_gemv(const double *LU, int lda, int b0, int bs, int i0, int i1,
-                                           double *x) {
+                                           double *x, int t) {
   if constexpr (ROWMAJOR) {
-    const int sub = threadIdx.x & 3;
-    for (int base = i0; base < i1; base += NT / 4) {
-      const int i = base + (threadIdx.x >> 2);
+    const int sub = t & 3;
+    for (int base = i0; base < i1; base += NTH / 4) {
+      const int i = base + (t >> 2);
       const bool ok = i < i1;
       double v[16];
 #pragma unroll
@@ -456,7 +461,7 @@ __device__ __forceinline__ void block_gemv(const double *LU, int lda, int b0, in
       if (ok && sub == 0) x[i] -= s;
     }
   } else {
-    for (int i = i0 + threadIdx.x; i < i1; i += NT) {
+    for (int i = i0 + t; i < i1; i += NTH) {
       double s = 0.0;
       for (int q0 = 0; q0 < bs; q0 += 16) {
         double v[16];
@@ -471,127 +476,158 @@ __device__ __forceinline__ void block_gemv(const double *LU, int lda, int b0, in
   }
 }
 
+// The chains of the four triangular solves on a staged diagonal block
+// (first wavefront only; x in LDS).
+// L y = b on the block, L unit lower.
+__device__ __forceinline__ void chain_l(const double *blk, int b0, int bs, double *x) {
+  const int lane = threadIdx.x & 63;
+  double xr = lane < bs ? x[b0 + lane] : 0.0;
+  for (int q0 = 0; q0 < bs - 1; q0 += 16) {
+    double o[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) o[u] = blk[lane * SBP + q0 + u];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (q0 + u < bs - 1) {
+        const double xq = bcast(xr, q0 + u);
+        if (lane > q0 + u) xr -= o[u] * xq;
+      }
+    }
+  }
+  if (lane < bs) x[b0 + lane] = xr;
+}
+
+// U x = y on the block; the unknown of row q is scaled by 1/U(q,q), formed
+// up front.
+__device__ __forceinline__ void chain_u(const double *blk, int b0, int bs, double *x) {
+  const int lane = threadIdx.x & 63;
+  double xr = lane < bs ? x[b0 + lane] : 0.0;
+  const double rd = lane < bs ? 1.0 / blk[lane * SBP + lane] : 0.0;
+  for (int q1 = bs; q1 > 0; q1 -= 16) {   // steps q = q1-1 .. q1-16
+    double o[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) o[u] = q1 - 1 - u >= 0 ? blk[lane * SBP + q1 - 1 - u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int q = q1 - 1 - u;
+      if (q >= 0) {
+        if (lane == q) xr *= rd;
+        const double xq = bcast(xr, q);
+        if (lane < q) xr -= o[u] * xq;
+      }
+    }
+  }
+  if (lane < bs) x[b0 + lane] = xr;
+}
+
+// U^T z = b on the block (lower, diagonal of U).
+__device__ __forceinline__ void chain_ut(const double *blk, int b0, int bs, double *x) {
+  const int lane = threadIdx.x & 63;
+  double xr = lane < bs ? x[b0 + lane] : 0.0;
+  const double rd = lane < bs ? 1.0 / blk[lane * SBP + lane] : 0.0;
+  for (int q0 = 0; q0 < bs; q0 += 16) {
+    double o[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) o[u] = blk[(q0 + u) * SBP + lane];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int q = q0 + u;
+      if (q < bs) {
+        if (lane == q) xr *= rd;
+        const double xq = bcast(xr, q);
+        if (lane > q && lane < bs) xr -= o[u] * xq;
+      }
+    }
+  }
+  if (lane < bs) x[b0 + lane] = xr;
+}
+
+// L^T w = z on the block (upper, unit diagonal).
+__device__ __forceinline__ void chain_lt(const double *blk, int b0, int bs, double *x) {
+  const int lane = threadIdx.x & 63;
+  double xr = lane < bs ? x[b0 + lane] : 0.0;
+  for (int q1 = bs; q1 > 1; q1 -= 16) {   // steps q = q1-1 .. max(1, q1-16)
+    double o[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) o[u] = q1 - 1 - u >= 1 ? blk[(q1 - 1 - u) * SBP + lane] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int q = q1 - 1 - u;
+      if (q >= 1) {
+        const double xq = bcast(xr, q);
+        if (lane < q) xr -= o[u] * xq;
+      }
+    }
+  }
+  if (lane < bs) x[b0 + lane] = xr;
+}
+
+// One blocked triangular solve, forward (FWD: blocks from the top) or
+// backward, with a one-block look-ahead: while the first wavefront runs the
+// chain of block k, the other wavefronts stage block k+1 and apply block
+// k-1's columns to the rows beyond block k; then the whole workgroup
+// applies block k's columns to the rows of block k+1, the only rows the
+// next chain needs. Every row receives the blocks' contributions in the
+// same order, each summed the same way, as without the look-ahead.
+// blk: 2 * SB * SBP doubles of LDS.
+template <int NT, bool ROWMAJOR, bool FWD, int CHAIN>
+__device__ __forceinline__ void tri_solve(const double *__restrict__ LU, int lda, int n, double *x,
+                                          double *blk) {
+  static_assert(NT >= 128 && NT % 64 == 0, "the look-ahead needs at least two wavefronts");
+  const int nb = (n + SB - 1) / SB;
+  auto b0_of = [&](int k) { return FWD ? k * SB : (n - (k + 1) * SB > 0 ? n - (k + 1) * SB : 0); };
+  auto bs_of = [&](int k) {
+    return FWD ? (k * SB + SB < n ? SB : n - k * SB) : n - k * SB - b0_of(k);
+  };
+  stage_block<NT>(LU, lda, b0_of(0), bs_of(0), blk, threadIdx.x);
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    const int b0 = b0_of(k), bs = bs_of(k);
+    double *cur = blk + (k & 1) * (SB * SBP);
+    if (threadIdx.x < 64) {
+      if (CHAIN == 0) chain_l(cur, b0, bs, x);
+      else if (CHAIN == 1) chain_u(cur, b0, bs, x);
+      else if (CHAIN == 2) chain_ut(cur, b0, bs, x);
+      else chain_lt(cur, b0, bs, x);
+    } else {
+      const int t = threadIdx.x - 64;
+      if (k + 1 < nb)
+        stage_block<NT - 64>(LU, lda, b0_of(k + 1), bs_of(k + 1),
+                             blk + ((k + 1) & 1) * (SB * SBP), t);
+      if (k >= 1) {
+        // block k-1's columns, rows beyond block k
+        const int p0 = b0_of(k - 1), ps = bs_of(k - 1);
+        if (FWD) block_gemv<NT - 64, ROWMAJOR>(LU, lda, p0, ps, b0 + bs, n, x, t);
+        else block_gemv<NT - 64, ROWMAJOR>(LU, lda, p0, ps, 0, b0, x, t);
+      }
+    }
+    __syncthreads();
+    if (k + 1 < nb) {
+      // block k's columns, rows of block k+1
+      const int n0 = b0_of(k + 1), ns_ = bs_of(k + 1);
+      block_gemv<NT, ROWMAJOR>(LU, lda, b0, bs, n0, n0 + ns_, x, threadIdx.x);
+      __syncthreads();
+    }
+  }
+}
+
 // Solves with the factors of wg_lu: A x = b (trans = false) or A^T x = b.
 // x (LDS, n doubles) holds b on entry and x on return; tmp (LDS, n
-// doubles) is scratch; blk: SB*SBP doubles of LDS.
+// doubles) is scratch; blk: 2 * SB * SBP doubles of LDS.
 template <int NT>
 __device__ __forceinline__ void wg_solve(const double *__restrict__ LU, int lda, int n,
                          const int *__restrict__ perm, double *x, double *tmp, bool trans,
                          double *blk) {
-  const int lane = threadIdx.x & 63;
-  const bool w0 = threadIdx.x < 64;
   if (!trans) {
     for (int i = threadIdx.x; i < n; i += NT) tmp[i] = x[perm[i]];
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += NT) x[i] = tmp[i];
-    // L y = P b, L unit lower
-    for (int b0 = 0; b0 < n; b0 += SB) {
-      const int bs = b0 + SB < n ? SB : n - b0;
-      stage_block<NT>(LU, lda, b0, bs, blk);
-      __syncthreads();
-      if (w0) {
-        double xr = lane < bs ? x[b0 + lane] : 0.0;
-        for (int q0 = 0; q0 < bs - 1; q0 += 16) {
-          double o[16];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) o[u] = blk[lane * SBP + q0 + u];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            if (q0 + u < bs - 1) {
-              const double xq = bcast(xr, q0 + u);
-              if (lane > q0 + u) xr -= o[u] * xq;
-            }
-          }
-        }
-        if (lane < bs) x[b0 + lane] = xr;
-      }
-      __syncthreads();
-      block_gemv<NT, true>(LU, lda, b0, bs, b0 + bs, n, x);
-      __syncthreads();
-    }
-    // U x = y; the unknown of row q is scaled by 1/U(q,q), formed up front
-    for (int bend = n; bend > 0; bend -= SB) {
-      const int b0 = bend - SB > 0 ? bend - SB : 0, bs = bend - b0;
-      stage_block<NT>(LU, lda, b0, bs, blk);
-      __syncthreads();
-      if (w0) {
-        double xr = lane < bs ? x[b0 + lane] : 0.0;
-        const double rd = lane < bs ? 1.0 / blk[lane * SBP + lane] : 0.0;
-        for (int q1 = bs; q1 > 0; q1 -= 16) {   // steps q = q1-1 .. q1-16
-          double o[16];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) o[u] = q1 - 1 - u >= 0 ? blk[lane * SBP + q1 - 1 - u] : 0.0;
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const int q = q1 - 1 - u;
-            if (q >= 0) {
-              if (lane == q) xr *= rd;
-              const double xq = bcast(xr, q);
-              if (lane < q) xr -= o[u] * xq;
-            }
-          }
-        }
-        if (lane < bs) x[b0 + lane] = xr;
-      }
-      __syncthreads();
-      block_gemv<NT, true>(LU, lda, b0, bs, 0, b0, x);
-      __syncthreads();
-    }
+    tri_solve<NT, true, true, 0>(LU, lda, n, x, blk);    // L y = P b (its first barrier
+                                                          // also orders the copy above)
+    tri_solve<NT, true, false, 1>(LU, lda, n, x, blk);   // U x = y
   } else {
-    // U^T z = b (lower, diagonal of U)
-    for (int b0 = 0; b0 < n; b0 += SB) {
-      const int bs = b0 + SB < n ? SB : n - b0;
-      stage_block<NT>(LU, lda, b0, bs, blk);
-      __syncthreads();
-      if (w0) {
-        double xr = lane < bs ? x[b0 + lane] : 0.0;
-        const double rd = lane < bs ? 1.0 / blk[lane * SBP + lane] : 0.0;
-        for (int q0 = 0; q0 < bs; q0 += 16) {
-          double o[16];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) o[u] = blk[(q0 + u) * SBP + lane];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const int q = q0 + u;
-            if (q < bs) {
-              if (lane == q) xr *= rd;
-              const double xq = bcast(xr, q);
-              if (lane > q && lane < bs) xr -= o[u] * xq;
-            }
-          }
-        }
-        if (lane < bs) x[b0 + lane] = xr;
-      }
-      __syncthreads();
-      block_gemv<NT, false>(LU, lda, b0, bs, b0 + bs, n, x);
-      __syncthreads();
-    }
-    // L^T w = z (upper, unit diagonal)
-    for (int bend = n; bend > 0; bend -= SB) {
-      const int b0 = bend - SB > 0 ? bend - SB : 0, bs = bend - b0;
-      stage_block<NT>(LU, lda, b0, bs, blk);
-      __syncthreads();
-      if (w0) {
-        double xr = lane < bs ? x[b0 + lane] : 0.0;
-        for (int q1 = bs; q1 > 1; q1 -= 16) {   // steps q = q1-1 .. max(1, q1-16)
-          double o[16];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) o[u] = q1 - 1 - u >= 1 ? blk[(q1 - 1 - u) * SBP + lane] : 0.0;
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const int q = q1 - 1 - u;
-            if (q >= 1) {
-              const double xq = bcast(xr, q);
-              if (lane < q) xr -= o[u] * xq;
-            }
-          }
-        }
-        if (lane < bs) x[b0 + lane] = xr;
-      }
-      __syncthreads();
-      block_gemv<NT, false>(LU, lda, b0, bs, 0, b0, x);
-      __syncthreads();
-    }
+    tri_solve<NT, false, true, 2>(LU, lda, n, x, blk);   // U^T z = b
+    tri_solve<NT, false, false, 3>(LU, lda, n, x, blk);  // L^T w = z
     // x = P^T w: x[perm[i]] = w[i]
     for (int i = threadIdx.x; i < n; i += NT) tmp[perm[i]] = x[i];
     __syncthreads();
