@@ -42,20 +42,25 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
   return s;
 }
 
-// A22 -= L21 U12 for the panel at k0 of width kw (A22 starts at kend =
-// k0 + kw). L21 is read from the LDS panel (row kw + r of `pan` is matrix
-// row kend + r), U12 and A22 from global memory. Each wave owns 32x32
-// blocks (2x2 tiles of 16x16); each tile is four v_mfma_f64_16x16x4
-// products (K = 16). Operand lanes: A[l%16][l/16], B[l/16][l%16]; result
-// element v of lane l is row l/16 + 4v, column l%16.
-template <int NT>
-__device__ __forceinline__ void trailing_block(double *__restrict__ A, int lda, int n, int k0,
-                                               int kw, const double *pan, int nb, int t,
-                                               d4_t (&acc)[2][2], double (&bop)[2][4], bool load) {
-  const int kend = k0 + kw;
+// Rank-16 updates of the region rows [R0, R1) x cols [C0, C1) of A by NSRC
+// factored panels, applied in order: A -= L_s U_s for panel s at column
+// ks[s] of width kws[s], with U_s = rows ks[s] .. ks[s]+kws[s]-1 of A and
+// L_s the panel's columns below them: read from A for every panel but the
+// last, whose L comes from the LDS panel `pan` when LDS_L is set (row
+// r - pk0 of pan is matrix row r). Each wave owns 32x32 blocks (2x2 tiles of 16x16); every
+// panel adds four v_mfma_f64_16x16x4 products (K = 16) per tile, so an
+// element takes exactly the products, in the same order, as one update per
+// panel would. Operand lanes: A[l%16][l/16], B[l/16][l%16]; result element
+// v of lane l is row l/16 + 4v, column l%16.
+template <int NT, int NSRC, bool LDS_L>
+__device__ __forceinline__ void region_block(double *__restrict__ A, int lda, int R0, int R1,
+                                             int C0, int C1, const int (&ks)[NSRC],
+                                             const int (&kws)[NSRC], const double *pan, int pk0,
+                                             int nbc, int t, d4_t (&acc)[2][2],
+                                             double (&bop)[NSRC][2][4], bool load) {
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  const int bi = t / nb, bj = t - bi * nb;
-  const int r0 = kend + 32 * bi, c0 = kend + 32 * bj;
+  const int bi = t / nbc, bj = t - bi * nbc;
+  const int r0 = R0 + 32 * bi, c0 = C0 + 32 * bj;
   if (load) {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -65,32 +70,40 @@ __device__ __forceinline__ void trailing_block(double *__restrict__ A, int lda, 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = r0 + 16 * a + lk + 4 * v;
-          acc[a][b][v] = (row < n && col < n) ? A[size_t(row) * lda + col] : 0.0;
+          acc[a][b][v] = (row < R1 && col < C1) ? A[size_t(row) * lda + col] : 0.0;
         }
       }
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int col = c0 + 16 * b + li;
+    for (int s = 0; s < NSRC; ++s)
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int kc = 4 * kk + lk;
-        bop[b][kk] = (kc < kw && col < n) ? A[size_t(k0 + kc) * lda + col] : 0.0;
+      for (int b = 0; b < 2; ++b) {
+        const int col = c0 + 16 * b + li;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int kc = 4 * kk + lk;
+          bop[s][b][kk] = (kc < kws[s] && col < C1) ? A[size_t(ks[s] + kc) * lda + col] : 0.0;
+        }
       }
-    }
     return;
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int pr = kw + 32 * bi + 16 * a + li;   // panel row of L21
-    const bool ok = kend + 32 * bi + 16 * a + li < n;
+  for (int s = 0; s < NSRC; ++s)
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const double aop = ok ? -pan[pr * PW + 4 * kk + lk] : 0.0;
+    for (int a = 0; a < 2; ++a) {
+      const int row = r0 + 16 * a + li;   // row of the L operand
+      const bool ok = row < R1;
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[b][kk], acc[a][b], 0, 0, 0);
+      for (int kk = 0; kk < 4; ++kk) {
+        const int kc = 4 * kk + lk;
+        double l = 0.0;
+        if (ok && kc < kws[s])
+          l = (LDS_L && s + 1 == NSRC) ? pan[(row - pk0) * PW + kc]
+                                       : A[size_t(row) * lda + ks[s] + kc];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-l, bop[s][b][kk], acc[a][b], 0, 0, 0);
+      }
     }
-  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -99,33 +112,42 @@ __device__ __forceinline__ void trailing_block(double *__restrict__ A, int lda, 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = r0 + 16 * a + lk + 4 * v;
-        if (row < n && col < n) A[size_t(row) * lda + col] = acc[a][b][v];
+        if (row < R1 && col < C1) A[size_t(row) * lda + col] = acc[a][b][v];
       }
     }
 }
 
-// A22 -= L21 U12 for the panel at k0 of width kw (A22 starts at kend =
-// k0 + kw). L21 is read from the LDS panel (row kw + r of `pan` is matrix
-// row kend + r), U12 and A22 from global memory. Each wave owns 32x32
-// blocks (2x2 tiles of 16x16, each four v_mfma_f64_16x16x4 products with
-// K = 16) and keeps two blocks' loads in flight. Operand lanes:
-// A[l%16][l/16], B[l/16][l%16]; result element v of lane l is row
-// l/16 + 4v, column l%16.
-template <int NT>
-__device__ __forceinline__ void trailing_update(double *__restrict__ A, int lda, int n, int k0,
-                                                int kw, const double *pan) {
-  const int m = n - (k0 + kw);
-  if (m <= 0) return;
-  const int nb = (m + 31) >> 5, nblk = nb * nb;
+// region_block over the whole region, each wave keeping two blocks' loads
+// in flight (one for two panels, whose operands double the loads).
+template <int NT, int NSRC, bool LDS_L>
+__device__ __forceinline__ void region_update(double *__restrict__ A, int lda, int R0, int R1,
+                                              int C0, int C1, const int (&ks)[NSRC],
+                                              const int (&kws)[NSRC], const double *pan, int pk0) {
+  if (R1 <= R0 || C1 <= C0) return;
+  const int nbr = (R1 - R0 + 31) >> 5, nbc = (C1 - C0 + 31) >> 5, nblk = nbr * nbc;
   constexpr int NW = NT / 64;
-  for (int t = threadIdx.x >> 6; t < nblk; t += 2 * NW) {
-    d4_t acc0[2][2], acc1[2][2];
-    double b0[2][4], b1[2][4];
-    const bool two = t + NW < nblk;
-    trailing_block<NT>(A, lda, n, k0, kw, pan, nb, t, acc0, b0, true);
-    if (two) trailing_block<NT>(A, lda, n, k0, kw, pan, nb, t + NW, acc1, b1, true);
-    trailing_block<NT>(A, lda, n, k0, kw, pan, nb, t, acc0, b0, false);
-    if (two) trailing_block<NT>(A, lda, n, k0, kw, pan, nb, t + NW, acc1, b1, false);
+  if constexpr (NSRC == 1) {
+    for (int t = threadIdx.x >> 6; t < nblk; t += 2 * NW) {
+      d4_t acc0[2][2], acc1[2][2];
+      double b0[1][2][4], b1[1][2][4];
+      const bool two = t + NW < nblk;
+      region_block<NT, 1, LDS_L>(A, lda, R0, R1, C0, C1, ks, kws, pan, pk0, nbc, t, acc0, b0, true);
+      if (two)
+        region_block<NT, 1, LDS_L>(A, lda, R0, R1, C0, C1, ks, kws, pan, pk0, nbc, t + NW, acc1, b1,
+                                   true);
+      region_block<NT, 1, LDS_L>(A, lda, R0, R1, C0, C1, ks, kws, pan, pk0, nbc, t, acc0, b0, false);
+      if (two)
+        region_block<NT, 1, LDS_L>(A, lda, R0, R1, C0, C1, ks, kws, pan, pk0, nbc, t + NW, acc1, b1,
+                                   false);
+    }
+  } else {
+    for (int t = threadIdx.x >> 6; t < nblk; t += NW) {
+      d4_t acc[2][2];
+      double bo[NSRC][2][4];
+      region_block<NT, NSRC, LDS_L>(A, lda, R0, R1, C0, C1, ks, kws, pan, pk0, nbc, t, acc, bo, true);
+      region_block<NT, NSRC, LDS_L>(A, lda, R0, R1, C0, C1, ks, kws, pan, pk0, nbc, t, acc, bo,
+                                    false);
+    }
   }
 }
 
@@ -303,6 +325,14 @@ __device__ __forceinline__ int wg_lu(double *__restrict__ A, int lda, int n, int
   int info = 0;
   int *mv = ipiv + PW;                       // [2 + 4 * PW] ints: count, pad, (dst, src) pairs
   double *inv = pan + size_t(n) * PW;        // PW x PW: L11^{-1} (first PW doubles: pivot row)
+  // Panels go in pairs, so that the trailing matrix is read and written once
+  // per two panels (rank-32 updates): the first panel of a pair updates only
+  // the second panel's columns before that panel is factored; after the
+  // second panel's row exchanges the first panel updates the second's U
+  // rows, and the rest of the trailing matrix then takes both panels'
+  // updates in one pass. Every element gets the same products in the same
+  // order as with one update per panel. pk >= 0: the pair's first panel.
+  int pk = -1, pkw = 0;
   for (int k0 = 0; k0 < n; k0 += PW) {
     const int kw = k0 + PW < n ? PW : n - k0;
     const int m = n - k0;
@@ -341,6 +371,13 @@ __device__ __forceinline__ int wg_lu(double *__restrict__ A, int lda, int n, int
         }
       }
     }
+    const int kend = k0 + kw;
+    if (pk >= 0) {
+      // the pair's first panel on this panel's (exchanged) U rows
+      __syncthreads();
+      const int ks[1] = {pk}, kws[1] = {pkw};
+      region_update<NT, 1, false>(A, lda, k0, kend, kend, n, ks, kws, pan, 0);
+    }
     // U12 = L11^{-1} A12 on the matrix cores: lane jc < PW forms column jc
     // of the inverse of the unit lower 16x16 L11 (identity beyond kw) in
     // registers, then every 16-column tile of A12 is one 16x16x16 product.
@@ -361,7 +398,6 @@ __device__ __forceinline__ int wg_lu(double *__restrict__ A, int lda, int n, int
     }
     __syncthreads();
     {
-      const int kend = k0 + kw;
       const int mt = (n - kend + 15) >> 4;
       const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
       for (int t = threadIdx.x >> 6; t < mt; t += NT / 64) {
@@ -384,7 +420,21 @@ __device__ __forceinline__ int wg_lu(double *__restrict__ A, int lda, int n, int
       }
     }
     __syncthreads();
-    trailing_update<NT>(A, lda, n, k0, kw, pan);
+    if (pk < 0) {
+      if (kend < n) {
+        // first of a pair: only the next panel's columns
+        const int kw1 = kend + PW < n ? PW : n - kend;
+        const int ks[1] = {k0}, kws[1] = {kw};
+        region_update<NT, 1, true>(A, lda, kend, n, kend, kend + kw1, ks, kws, pan, k0);
+        pk = k0;
+        pkw = kw;
+      }
+    } else {
+      // second of a pair: both panels on the rest of the trailing matrix
+      const int ks[2] = {pk, k0}, kws[2] = {pkw, kw};
+      region_update<NT, 2, true>(A, lda, kend, n, kend, n, ks, kws, pan, k0);
+      pk = -1;
+    }
     __syncthreads();
   }
   // permutation from the swap sequence (once per factorisation)
