@@ -18,6 +18,7 @@ namespace ac {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int PW = 16;   // LU panel width
+constexpr int LU_GROUP = 4;   // panels per trailing-matrix pass
 constexpr int SB = 64;        // triangular-solve block
 constexpr int SBP = SB + 1;   // its LDS row stride (odd: row-wise lane reads avoid bank conflicts)
 
@@ -42,112 +43,111 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
   return s;
 }
 
-// Rank-16 updates of the region rows [R0, R1) x cols [C0, C1) of A by NSRC
-// factored panels, applied in order: A -= L_s U_s for panel s at column
-// ks[s] of width kws[s], with U_s = rows ks[s] .. ks[s]+kws[s]-1 of A and
-// L_s the panel's columns below them: read from A for every panel but the
-// last, whose L comes from the LDS panel `pan` when LDS_L is set (row
-// r - pk0 of pan is matrix row r). Each wave owns 32x32 blocks (2x2 tiles of 16x16); every
-// panel adds four v_mfma_f64_16x16x4 products (K = 16) per tile, so an
-// element takes exactly the products, in the same order, as one update per
-// panel would. Operand lanes: A[l%16][l/16], B[l/16][l%16]; result element
-// v of lane l is row l/16 + 4v, column l%16.
-template <int NT, int NSRC, bool LDS_L>
-__device__ __forceinline__ void region_block(double *__restrict__ A, int lda, int R0, int R1,
-                                             int C0, int C1, const int (&ks)[NSRC],
-                                             const int (&kws)[NSRC], const double *pan, int pk0,
-                                             int nbc, int t, d4_t (&acc)[2][2],
-                                             double (&bop)[NSRC][2][4], bool load) {
+// Rank-16 updates of the region rows [R0, R1) x cols [C0, C1) of A by the
+// nsrc full-width panels at columns K0, K0 + PW, ..., applied in that
+// order: A -= L_s U_s, with U_s the panel's PW rows of A and L_s its
+// columns below them, read from A, or for the last panel from the LDS panel
+// `pan` when lds_last is set (row r - pk0 of pan is matrix row r). Each
+// wave owns 32x32 blocks (2x2 tiles of 16x16), two at a time; every panel
+// adds four v_mfma_f64_16x16x4 products (K = 16) per tile, so an element
+// takes exactly the products, in the same order, as one update per panel
+// would. Operand lanes: A[l%16][l/16], B[l/16][l%16]; result element v of
+// lane l is row l/16 + 4v, column l%16.
+struct RegionBlock {
+  int r0, c0;
+  d4_t acc[2][2];
+  double bop[2][4];
+};
+
+__device__ __forceinline__ void rb_load(RegionBlock &B, const double *__restrict__ A, int lda,
+                                        int R1, int C1) {
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  const int bi = t / nbc, bj = t - bi * nbc;
-  const int r0 = R0 + 32 * bi, c0 = C0 + 32 * bj;
-  if (load) {
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int col = c0 + 16 * b + li;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = r0 + 16 * a + lk + 4 * v;
-          acc[a][b][v] = (row < R1 && col < C1) ? A[size_t(row) * lda + col] : 0.0;
-        }
-      }
-#pragma unroll
-    for (int s = 0; s < NSRC; ++s)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int col = c0 + 16 * b + li;
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int kc = 4 * kk + lk;
-          bop[s][b][kk] = (kc < kws[s] && col < C1) ? A[size_t(ks[s] + kc) * lda + col] : 0.0;
-        }
-      }
-    return;
-  }
-#pragma unroll
-  for (int s = 0; s < NSRC; ++s)
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int row = r0 + 16 * a + li;   // row of the L operand
-      const bool ok = row < R1;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int kc = 4 * kk + lk;
-        double l = 0.0;
-        if (ok && kc < kws[s])
-          l = (LDS_L && s + 1 == NSRC) ? pan[(row - pk0) * PW + kc]
-                                       : A[size_t(row) * lda + ks[s] + kc];
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-l, bop[s][b][kk], acc[a][b], 0, 0, 0);
-      }
-    }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const int col = c0 + 16 * b + li;
+      const int col = B.c0 + 16 * b + li;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = r0 + 16 * a + lk + 4 * v;
-        if (row < R1 && col < C1) A[size_t(row) * lda + col] = acc[a][b][v];
+        const int row = B.r0 + 16 * a + lk + 4 * v;
+        B.acc[a][b][v] = (row < R1 && col < C1) ? A[size_t(row) * lda + col] : 0.0;
       }
     }
 }
 
-// region_block over the whole region, each wave keeping two blocks' loads
-// in flight (one for two panels, whose operands double the loads).
-template <int NT, int NSRC, bool LDS_L>
+__device__ __forceinline__ void rb_load_u(RegionBlock &B, const double *__restrict__ A, int lda,
+                                          int C1, int ks) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int col = B.c0 + 16 * b + li;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      B.bop[b][kk] = col < C1 ? A[size_t(ks + 4 * kk + lk) * lda + col] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void rb_mfma(RegionBlock &B, const double *__restrict__ A, int lda,
+                                        int R1, int ks, const double *pan, int pk0, bool lds) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int row = B.r0 + 16 * a + li;   // row of the L operand
+    const bool ok = row < R1;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int kc = 4 * kk + lk;
+      double l = 0.0;
+      if (ok) l = lds ? pan[(row - pk0) * PW + kc] : A[size_t(row) * lda + ks + kc];
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        B.acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-l, B.bop[b][kk], B.acc[a][b], 0, 0, 0);
+    }
+  }
+}
+
+__device__ __forceinline__ void rb_store(const RegionBlock &B, double *__restrict__ A, int lda,
+                                         int R1, int C1) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = B.c0 + 16 * b + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = B.r0 + 16 * a + lk + 4 * v;
+        if (row < R1 && col < C1) A[size_t(row) * lda + col] = B.acc[a][b][v];
+      }
+    }
+}
+
+template <int NT>
 __device__ __forceinline__ void region_update(double *__restrict__ A, int lda, int R0, int R1,
-                                              int C0, int C1, const int (&ks)[NSRC],
-                                              const int (&kws)[NSRC], const double *pan, int pk0) {
-  if (R1 <= R0 || C1 <= C0) return;
-  const int nbr = (R1 - R0 + 31) >> 5, nbc = (C1 - C0 + 31) >> 5, nblk = nbr * nbc;
+                                              int C0, int C1, int K0, int nsrc, const double *pan,
+                                              int pk0, bool lds_last) {
+  if (R1 <= R0 || C1 <= C0 || nsrc <= 0) return;
+  const int nbc = (C1 - C0 + 31) >> 5, nblk = ((R1 - R0 + 31) >> 5) * nbc;
   constexpr int NW = NT / 64;
-  if constexpr (NSRC == 1) {
-    for (int t = threadIdx.x >> 6; t < nblk; t += 2 * NW) {
-      d4_t acc0[2][2], acc1[2][2];
-      double b0[1][2][4], b1[1][2][4];
-      const bool two = t + NW < nblk;
-      region_block<NT, 1, LDS_L>(A, lda, R0, R1, C0, C1, ks, kws, pan, pk0, nbc, t, acc0, b0, true);
-      if (two)
-        region_block<NT, 1, LDS_L>(A, lda, R0, R1, C0, C1, ks, kws, pan, pk0, nbc, t + NW, acc1, b1,
-                                   true);
-      region_block<NT, 1, LDS_L>(A, lda, R0, R1, C0, C1, ks, kws, pan, pk0, nbc, t, acc0, b0, false);
-      if (two)
-        region_block<NT, 1, LDS_L>(A, lda, R0, R1, C0, C1, ks, kws, pan, pk0, nbc, t + NW, acc1, b1,
-                                   false);
+  for (int t = threadIdx.x >> 6; t < nblk; t += 2 * NW) {
+    const bool two = t + NW < nblk;
+    RegionBlock B0, B1;
+    B0.r0 = R0 + 32 * (t / nbc);
+    B0.c0 = C0 + 32 * (t % nbc);
+    B1.r0 = R0 + 32 * ((t + NW) / nbc);
+    B1.c0 = C0 + 32 * ((t + NW) % nbc);
+    rb_load(B0, A, lda, R1, C1);
+    if (two) rb_load(B1, A, lda, R1, C1);
+    for (int s = 0; s < nsrc; ++s) {
+      const int ks = K0 + PW * s;
+      const bool lds = lds_last && s + 1 == nsrc;
+      rb_load_u(B0, A, lda, C1, ks);
+      if (two) rb_load_u(B1, A, lda, C1, ks);
+      rb_mfma(B0, A, lda, R1, ks, pan, pk0, lds);
+      if (two) rb_mfma(B1, A, lda, R1, ks, pan, pk0, lds);
     }
-  } else {
-    for (int t = threadIdx.x >> 6; t < nblk; t += NW) {
-      d4_t acc[2][2];
-      double bo[NSRC][2][4];
-      region_block<NT, NSRC, LDS_L>(A, lda, R0, R1, C0, C1, ks, kws, pan, pk0, nbc, t, acc, bo, true);
-      region_block<NT, NSRC, LDS_L>(A, lda, R0, R1, C0, C1, ks, kws, pan, pk0, nbc, t, acc, bo,
-                                    false);
-    }
+    rb_store(B0, A, lda, R1, C1);
+    if (two) rb_store(B1, A, lda, R1, C1);
   }
 }
 
@@ -325,17 +325,20 @@ __device__ __forceinline__ int wg_lu(double *__restrict__ A, int lda, int n, int
   int info = 0;
   int *mv = ipiv + PW;                       // [2 + 4 * PW] ints: count, pad, (dst, src) pairs
   double *inv = pan + size_t(n) * PW;        // PW x PW: L11^{-1} (first PW doubles: pivot row)
-  // Panels go in pairs, so that the trailing matrix is read and written once
-  // per two panels (rank-32 updates): the first panel of a pair updates only
-  // the second panel's columns before that panel is factored; after the
-  // second panel's row exchanges the first panel updates the second's U
-  // rows, and the rest of the trailing matrix then takes both panels'
-  // updates in one pass. Every element gets the same products in the same
-  // order as with one update per panel. pk >= 0: the pair's first panel.
-  int pk = -1, pkw = 0;
+  // Panels go in groups of LU_GROUP, so that the trailing matrix is read and
+  // written once per group (rank-16 LU_GROUP updates): before a panel is
+  // factored, the group's earlier panels update its columns; after its row
+  // exchanges they update its U rows; once the group is complete, the rest
+  // of the trailing matrix takes all of the group's updates in one pass.
+  // Every element gets the same products in the same order as with one
+  // update per panel. Panels of a group are full width except possibly the
+  // matrix's last. K0: the group's first column; gi: its panels so far.
+  int K0 = 0, gi = 0;
   for (int k0 = 0; k0 < n; k0 += PW) {
     const int kw = k0 + PW < n ? PW : n - k0;
     const int m = n - k0;
+    // the group's earlier panels on this panel's columns
+    region_update<NT>(A, lda, k0, n, k0, k0 + kw, K0, gi, pan, 0, false);
     if (threadIdx.x == 0) mv[0] = 0;
     __syncthreads();
     if (m <= NT)
@@ -372,11 +375,10 @@ __device__ __forceinline__ int wg_lu(double *__restrict__ A, int lda, int n, int
       }
     }
     const int kend = k0 + kw;
-    if (pk >= 0) {
-      // the pair's first panel on this panel's (exchanged) U rows
+    if (gi > 0) {
+      // the group's earlier panels on this panel's (exchanged) U rows
       __syncthreads();
-      const int ks[1] = {pk}, kws[1] = {pkw};
-      region_update<NT, 1, false>(A, lda, k0, kend, kend, n, ks, kws, pan, 0);
+      region_update<NT>(A, lda, k0, kend, kend, n, K0, gi, pan, 0, false);
     }
     // U12 = L11^{-1} A12 on the matrix cores: lane jc < PW forms column jc
     // of the inverse of the unit lower 16x16 L11 (identity beyond kw) in
@@ -420,20 +422,12 @@ __device__ __forceinline__ int wg_lu(double *__restrict__ A, int lda, int n, int
       }
     }
     __syncthreads();
-    if (pk < 0) {
-      if (kend < n) {
-        // first of a pair: only the next panel's columns
-        const int kw1 = kend + PW < n ? PW : n - kend;
-        const int ks[1] = {k0}, kws[1] = {kw};
-        region_update<NT, 1, true>(A, lda, kend, n, kend, kend + kw1, ks, kws, pan, k0);
-        pk = k0;
-        pkw = kw;
-      }
-    } else {
-      // second of a pair: both panels on the rest of the trailing matrix
-      const int ks[2] = {pk, k0}, kws[2] = {pkw, kw};
-      region_update<NT, 2, true>(A, lda, kend, n, kend, n, ks, kws, pan, k0);
-      pk = -1;
+    if (++gi == LU_GROUP || kend >= n) {
+      // the whole group on the rest of the trailing matrix (this panel's L
+      // from LDS)
+      region_update<NT>(A, lda, kend, n, kend, n, K0, gi, pan, k0, true);
+      K0 = kend;
+      gi = 0;
     }
     __syncthreads();
   }
