@@ -34,7 +34,7 @@ def _t(torch, a, dtype=None):
 
 # ------------------------------------------------------------------ LU
 
-@pytest.mark.parametrize("n", [1, 5, 16, 33, 100, 470, 513, 700, 1024])
+@pytest.mark.parametrize("n", [1, 5, 16, 33, 48, 64, 65, 80, 100, 129, 200, 470, 513, 700, 1024])
 def test_lu_matches_oracle(acm, torch_dev, oracle_mod, n):
     torch = torch_dev
     rng = np.random.default_rng(n)
