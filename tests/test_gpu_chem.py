@@ -230,3 +230,26 @@ def test_autotune_picks_a_working_configuration(acm, torch_dev, oracle_mod, medi
     jv = N.jac(_t(torch, y[:40]), _t(torch, T[:40])).cpu().numpy()
     J, abJ = oracle_mod.jac_dense(medium_net, y[:40], T[:40], with_abs=True)
     _close(jv, _jac_at_pattern(N, J), _jac_at_pattern(N, abJ))
+
+
+def test_two_cell_kernels_independent_of_partner(acm, torch_dev, medium_net, med_cells):
+    """The RHS, Jacobian and VJP run two cells per pass. A cell's values must
+    not depend on which cell shares its pass, or on having none: cells 1..6
+    computed in the passes (0,1),(2,3),(4,5),(6) and again in (1,2),(3,4),
+    (5,6),(7) agree bit for bit, and the RHS equals the one-cell kernel's."""
+    torch = torch_dev
+    N = acm.Network.from_synth(medium_net)
+    y, T = med_cells.y0[:8], med_cells.T[:8]
+    v = np.random.default_rng(4).standard_normal(y.shape)
+    a = (_t(torch, y[:7]), _t(torch, T[:7]), _t(torch, v[:7]))
+    b = (_t(torch, y[1:8]), _t(torch, T[1:8]), _t(torch, v[1:8]))
+    fa, fb = N.rhs(a[0], a[1]).cpu().numpy(), N.rhs(b[0], b[1]).cpu().numpy()
+    assert np.array_equal(fa[1:7], fb[0:6])
+    for c in (0, 6):
+        one = N.rhs(_t(torch, y[c:c + 1]), _t(torch, T[c:c + 1])).cpu().numpy()
+        assert np.array_equal(one[0], fa[c])
+    ja, jb = N.jac(a[0], a[1]).cpu().numpy(), N.jac(b[0], b[1]).cpu().numpy()
+    assert np.array_equal(ja[1:7], jb[0:6])
+    ga, _ = N.vjp(*a)
+    gb, _ = N.vjp(*b)
+    assert np.array_equal(ga.cpu().numpy()[1:7], gb.cpu().numpy()[0:6])
