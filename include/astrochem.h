@@ -223,6 +223,10 @@ typedef struct {
   double h0;          /* first step [s]; <= 0 selects it (Hairer-Norsett-Wanner) */
   int32_t q_max;      /* 1..5; 1 is adaptive backward Euler */
   int32_t max_steps;  /* accepted-step budget per cell */
+  int32_t adj_recompute; /* adjoint only: 1 recomputes every 64-step segment from
+                            its checkpoint; 0 keeps every converged state of the
+                            forward replay instead when they fit (see
+                            ac_integrate_adjoint) */
 } ac_integ_opts;
 
 /* Per-cell counters written by the integrator ([n_cells][AC_NSTAT]). */
@@ -293,10 +297,16 @@ ac_status ac_integrate_plain(ac_ws *ws, const double *log_alpha, int64_t n_cells
  *   cell_stats [n_cells][AC_NSTAT] DEVICE or NULL: steps reversed, Newton
  *     iterations of the replays, Jacobians, factorisations and RHS
  *     evaluations (the rejection and order fields are 0).
- * Only rtol and atol of opts are used (they scale the replay's convergence
- * test). The workspace grows its checkpoint store on the first call with a
- * larger tape_cap (a device allocation, after synchronising the stream);
- * about 64 tape_cap n_species bytes per slot. Errors: AC_EINVAL for bad
+ * Only rtol, atol and adj_recompute of opts are used (the tolerances scale
+ * the replay's convergence test). With adj_recompute = 0 the forward replay
+ * keeps the converged state of every step when tape_cap n_species 8 bytes
+ * per slot come to at most 8 GiB in all, and the reverse sweep reads them
+ * instead of recomputing each segment; the recomputed states are bitwise
+ * the same, so only the time and the replay counters in cell_stats change.
+ * The workspace grows its checkpoint store on the first call with a larger
+ * tape_cap or the other state mode (a device allocation, after
+ * synchronising the stream); about 64 tape_cap n_species bytes per slot,
+ * plus 8 tape_cap n_species when every state is kept. Errors: AC_EINVAL for bad
  * sizes or NULL required arrays, AC_ENOMEM/AC_EHIP for allocation or
  * launch failures. */
 ac_status ac_integrate_adjoint(ac_ws *ws, const double *log_alpha, int64_t n_cells,

@@ -133,7 +133,7 @@ def _check_dev(t, shape, name: str):
 
 class IntegOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h0", C.c_double),
-                ("q_max", C.c_int32), ("max_steps", C.c_int32)]
+                ("q_max", C.c_int32), ("max_steps", C.c_int32), ("adj_recompute", C.c_int32)]
 
 
 EVENT_DTYPE = np.dtype([("type", np.int32), ("q", np.int32), ("val", np.float64)])
@@ -369,7 +369,7 @@ class Workspace:
         dev = y.device
         status = torch.empty(n, dtype=torch.int32, device=dev)
         stats = torch.empty((n, NSTAT), dtype=torch.int32, device=dev)
-        o = IntegOpts(float(rtol), float(atol), float(h0), int(q_max), int(max_steps))
+        o = IntegOpts(float(rtol), float(atol), float(h0), int(q_max), int(max_steps), 0)
         out = {"status": status, "stats": stats}
         if plain:
             check(lib.ac_integrate_plain(self.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T),
@@ -388,14 +388,16 @@ class Workspace:
 
 
     def adjoint(self, y0, T, tape, tape_len, lam, rtol=1e-6, atol=1e-20, log_alpha=None,
-                want_glog=True, want_cells=False, want_y=False, stream=None):
+                want_glog=True, want_cells=False, want_y=False, recompute=False, stream=None):
         """Discrete adjoint (ac_integrate_adjoint) of L = sum <lam, y(t_end)>
         over the recorded tape of an earlier integrate(..., tape_cap=...).
         Returns dict of device tensors: dL_dy0 [n, ns], status [n], stats
         [n, NSTAT] (steps reversed, replay Newton iterations, Jacobians,
         factorisations, RHS evaluations) and, as
         requested, dL_dlogalpha [nr] (summed over cells in cell order),
-        g_cells [n, nr] and the replayed y_final [n, ns]."""
+        g_cells [n, nr] and the replayed y_final [n, ns]. recompute=True
+        recomputes every 64-step segment from its checkpoint instead of
+        keeping every converged state (same results, less memory)."""
         import torch
         n, ns, nr = T.shape[0], self.net.n_species, self.net.n_reactions
         _check_dev(T, (n,), "T")
@@ -423,7 +425,7 @@ class Workspace:
         if want_y:
             yf = torch.empty_like(y0)
             out["y_final"] = yf
-        o = IntegOpts(float(rtol), float(atol), 0.0, 5, 1)
+        o = IntegOpts(float(rtol), float(atol), 0.0, 5, 1, 1 if recompute else 0)
         check(lib.ac_integrate_adjoint(self.handle, _ptr(log_alpha), n, _ptr(y0), _ptr(T),
                                        C.byref(o), _ptr(tape), int(tape.shape[1]),
                                        _ptr(tape_len), _ptr(lam), _ptr(yf), _ptr(gy0),

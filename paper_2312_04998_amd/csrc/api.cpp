@@ -566,19 +566,26 @@ ac_status ac_integrate_plain(ac_ws *ws, const double *log_alpha, int64_t n_cells
 }
 
 // Adjoint slots for tapes of up to tape_cap events: checkpoint store
-// (tape_cap / CK_EVERY + 1 difference arrays), one segment of converged
-// states and the adjoint difference array per slot.
-static ac_status adj_reserve(ac_ws *ws, int tape_cap, hipStream_t st) {
+// (tape_cap / CK_EVERY + 1 difference arrays), the converged states of one
+// segment or, when all_states is asked for and fits, of every step, and
+// the adjoint difference array per slot.
+constexpr size_t ADJ_ALL_STATES_BUDGET = size_t(8) << 30;   // bytes over all slots
+static ac_status adj_reserve(ac_ws *ws, int tape_cap, bool all_states, hipStream_t st) {
   const int ckcap = tape_cap / ac::CK_EVERY + 1;
-  if (ws->adj_buf && ws->A.ckcap >= ckcap) return AC_OK;
   const int ns = ws->net->d.ns;
+  const size_t S = size_t(ws->n_slots);
+  if (all_states && sizeof(double) * size_t(tape_cap) * ns * S > ADJ_ALL_STATES_BUDGET)
+    all_states = false;
+  const int segcap = all_states ? tape_cap : ac::CK_EVERY;
+  if (ws->adj_buf && ws->A.ckcap >= ckcap && ws->A.segcap >= segcap &&
+      (ws->A.all_states != 0) == all_states)
+    return AC_OK;
   auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t dsz = size_t(8) * ns;
   const size_t db_b = r256(sizeof(double) * dsz);
   const size_t ck_b = r256(sizeof(double) * dsz * size_t(ckcap));
-  const size_t sy_b = r256(sizeof(double) * size_t(ac::CK_EVERY) * ns);
+  const size_t sy_b = r256(sizeof(double) * size_t(segcap) * ns);
   const size_t ce_b = r256(sizeof(int) * size_t(ckcap));
-  const size_t S = size_t(ws->n_slots);
   const size_t bytes = (db_b + ck_b + sy_b + ce_b) * S;
   if (ws->adj_buf) {
     hipError_t e = hipStreamSynchronize(st);
@@ -606,6 +613,8 @@ static ac_status adj_reserve(ac_ws *ws, int tape_cap, hipStream_t st) {
   A.segy_stride = sy_b / sizeof(double);
   A.ckev_stride = ce_b / sizeof(int);
   A.ckcap = ckcap;
+  A.segcap = segcap;
+  A.all_states = all_states ? 1 : 0;
   return AC_OK;
 }
 
@@ -623,7 +632,7 @@ ac_status ac_integrate_adjoint(ac_ws *ws, const double *log_alpha, int64_t n_cel
     return fail(AC_EINVAL, "dL_dlogalpha needs the per-cell rows g_cells");
   hipStream_t st = hipStream_t(stream);
   if (n_cells) {
-    if (ac_status s = adj_reserve(ws, tape_cap, st)) return s;
+    if (ac_status s = adj_reserve(ws, tape_cap, opts->adj_recompute == 0, st)) return s;
     ac::BdfParams P{opts->rtol, opts->atol, opts->h0, 0.0, opts->q_max, opts->max_steps};
     ac::AdjIO io{reinterpret_cast<const ac::AcEvent *>(tape), tape_len, tape_cap, y0, T, lambda,
                  y_final, dL_dy0, g_cells, cell_status, cell_stats};

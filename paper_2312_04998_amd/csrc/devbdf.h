@@ -54,6 +54,8 @@ struct AdjView {
   int *ckev;
   size_t db_stride, ck_stride, segy_stride, ckev_stride;
   int ckcap;
+  int segcap;       // converged states per slot: CK_EVERY, or every step of a tape
+  int all_states;   // 1: the forward pass keeps every state, so no segment is recomputed
 };
 
 struct AdjIO {

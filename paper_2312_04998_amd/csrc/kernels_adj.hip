@@ -273,6 +273,8 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
             cM = 0.0;
           }
           replay_step<NT>(cx, v, E.q, E.val, P.rtol, P.atol, ns, cM);
+          if (A.all_states)   // nstep < nev <= cap = segcap
+            for (int x = threadIdx.x; x < ns; x += NT) segY[size_t(nstep) * ns + x] = yn[x];
           ++nstep;
         } else if (E.type == EV_RESCALE) {
           rescale_diffs<NT>(cx, E.q, E.val, ns);
@@ -290,20 +292,27 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
       // reverse sweep, one checkpointed segment at a time
       int e_end = nev;
       for (int s = nck - 1; s >= 0; --s) {
-        const double *src = ck + size_t(s) * dsz;
-        for (size_t i = threadIdx.x; i < dsz; i += NT) cx.D[i] = src[i];
-        __syncthreads();
         const int e0 = ckev[s];
         int i = 0;
-        double cM = 0.0;
-        for (int e = e0; e < e_end; ++e) {
-          const AcEvent E = ev[e];
-          if (E.type == EV_STEP) {
-            replay_step<NT>(cx, v, E.q, E.val, P.rtol, P.atol, ns, cM);
-            for (int x = threadIdx.x; x < ns; x += NT) segY[size_t(i) * ns + x] = yn[x];
-            ++i;
-          } else if (E.type == EV_RESCALE) {
-            rescale_diffs<NT>(cx, E.q, E.val, ns);
+        const double *sy = segY;
+        if (A.all_states) {
+          // the forward pass kept them: segment s is steps s*CK_EVERY ...
+          sy = segY + size_t(s) * CK_EVERY * ns;
+          i = s + 1 < nck ? CK_EVERY : nstep - s * CK_EVERY;
+        } else {
+          const double *src = ck + size_t(s) * dsz;
+          for (size_t k = threadIdx.x; k < dsz; k += NT) cx.D[k] = src[k];
+          __syncthreads();
+          double cM = 0.0;
+          for (int e = e0; e < e_end; ++e) {
+            const AcEvent E = ev[e];
+            if (E.type == EV_STEP) {
+              replay_step<NT>(cx, v, E.q, E.val, P.rtol, P.atol, ns, cM);
+              for (int x = threadIdx.x; x < ns; x += NT) segY[size_t(i) * ns + x] = yn[x];
+              ++i;
+            } else if (E.type == EV_RESCALE) {
+              rescale_diffs<NT>(cx, E.q, E.val, ns);
+            }
           }
         }
         __syncthreads();
@@ -311,7 +320,7 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
           const AcEvent E = ev[e];
           if (E.type == EV_STEP) {
             --i;
-            for (int x = threadIdx.x; x < ns; x += NT) yn[x] = segY[size_t(i) * ns + x];
+            for (int x = threadIdx.x; x < ns; x += NT) yn[x] = sy[size_t(i) * ns + x];
             __syncthreads();
             reverse_step<NT>(cx, v, Db, E.q, E.val, ns, grow);
             cx.cnt[ST_STEPS]++;

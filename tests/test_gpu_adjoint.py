@@ -213,3 +213,35 @@ def test_adjoint_edge_cases(acm, oracle_mod):
     np.testing.assert_array_equal(out["dL_dy0"].cpu().numpy(), lam)
     np.testing.assert_array_equal(out["g_cells"].cpu().numpy(), 0.0)
     np.testing.assert_array_equal(out["y_final"].cpu().numpy()[1], y0[1])
+
+
+@pytest.mark.parametrize("which", ["tiny", "medium"])
+def test_adjoint_kept_states_equal_recomputed(acm, oracle_mod, which):
+    """Keeping every converged state of the forward replay (the default) and
+    recomputing each 64-step segment from its checkpoint give bitwise equal
+    gradients, final states and statuses; only the replay counters differ
+    (the kept-state run does one replay per step). Tapes long enough for
+    several segments."""
+    import torch
+    if which == "tiny":
+        net, cells = synthnet.workload("tiny", n_cells=5)
+        t_end, n, K = 1e5 * YEAR_S, 5, 100000
+    else:
+        net, cells = synthnet.workload("medium", n_cells=6)
+        t_end, n, K = 1e6 * YEAR_S, 6, 200
+    ref = oracle_mod.bdf(net, cells.y0[:n], cells.T[:n], t_end, max_steps=K, tape_cap=4096)
+    assert int(ref["tape_len"].max()) > 3 * 64
+    N = acm.Network.from_synth(net)
+    ws = acm.Workspace(N, n_slots=3)
+    lam = np.random.default_rng(11).standard_normal(cells.y0[:n].shape)
+    args = (_t(cells.y0[:n]), _t(cells.T[:n]), acm.tape_from_numpy(ref["tape"]),
+            _t(ref["tape_len"], np.int32), _t(lam))
+    a = ws.adjoint(*args, want_cells=True, want_y=True)
+    b = ws.adjoint(*args, want_cells=True, want_y=True, recompute=True)
+    c = ws.adjoint(*args, want_cells=True, want_y=True)
+    for k in ("dL_dy0", "g_cells", "dL_dlogalpha", "y_final", "status"):
+        assert torch.equal(a[k], b[k]), k
+        assert torch.equal(a[k], c[k]), k
+    sa, sb = a["stats"].cpu().numpy(), b["stats"].cpu().numpy()
+    assert np.array_equal(sa[:, 0], sb[:, 0])          # steps reversed
+    assert (sa[:, 3] < sb[:, 3]).all()                  # fewer replay Newton iterations
