@@ -180,6 +180,14 @@ ac_status ac_rhs_k(const ac_net *net, int64_t n_cells, const double *k, const do
 ac_status ac_jac(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *y,
                  const double *T, double *jvals, ac_stream stream);
 
+/* ac_rhs and ac_jac in one call: dydt [n_cells][n_species] and jvals
+ * [n_cells][nnz_j], bit-identical to the two calls. With the SELL layout
+ * one kernel computes the coefficients once per cell for both (the
+ * Newton step needs both at the same state); otherwise it issues the two
+ * launches. Errors as ac_rhs / ac_jac. */
+ac_status ac_rhs_jac(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *y,
+                     const double *T, double *dydt, double *jvals, ac_stream stream);
+
 /* Vector-Jacobian products for cotangents v [n_cells][n_species]:
  *   gy[c][a] = sum_i v[c][i] J_ia                            (gy may be NULL)
  *   g_logalpha[j] = sum_c sum_i v[c][i] d(dydt_i)/d(ln alpha_j)

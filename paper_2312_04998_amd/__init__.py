@@ -45,7 +45,7 @@ class NetDesc(C.Structure):
 
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2312_04998_amd.build`")
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2312_04998_amd/build.py`")
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, st = C.c_void_p, C.c_int32, C.c_int64, C.c_int
     sig = {
@@ -60,6 +60,7 @@ def _load() -> C.CDLL:
         "ac_rhs": [vp, vp, i64, vp, vp, vp, vp],
         "ac_rhs_k": [vp, i64, vp, vp, vp, vp],
         "ac_jac": [vp, vp, i64, vp, vp, vp, vp],
+        "ac_rhs_jac": [vp, vp, i64, vp, vp, vp, vp, vp],
         "ac_vjp": [vp, vp, i64, vp, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
@@ -284,6 +285,16 @@ def ac_jac(net: Network, log_alpha, y, T, jvals, stream=None):
         _check_dev(log_alpha, (net.n_reactions,), "log_alpha")
     check(lib.ac_jac(net.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T), _ptr(jvals),
                      _stream(stream)), "ac_jac")
+
+
+def ac_rhs_jac(net: Network, log_alpha, y, T, dydt, jvals, stream=None):
+    n = _cells(net, y, T)
+    _check_dev(dydt, (n, net.n_species), "dydt")
+    _check_dev(jvals, (n, net.nnz_j), "jvals")
+    if log_alpha is not None:
+        _check_dev(log_alpha, (net.n_reactions,), "log_alpha")
+    check(lib.ac_rhs_jac(net.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T), _ptr(dydt),
+                         _ptr(jvals), _stream(stream)), "ac_rhs_jac")
 
 
 def ac_vjp(net: Network, log_alpha, y, T, v, gy, g_logalpha, stream=None):

@@ -1,6 +1,8 @@
 """Builds libastrochem.so for gfx950 with hipcc (in-tree, no JIT cache).
 
-    python -m paper_2312_04998_amd.build
+    python paper_2312_04998_amd/build.py
+
+(Run it by path: importing the package loads the library.)
 """
 from __future__ import annotations
 

@@ -388,6 +388,16 @@ ac_status ac_jac(const ac_net *net, const double *log_alpha, int64_t n_cells, co
   return e == hipSuccess ? AC_OK : hip_fail(e, "ac_jac launch");
 }
 
+ac_status ac_rhs_jac(const ac_net *net, const double *log_alpha, int64_t n_cells,
+                     const double *y, const double *T, double *dydt, double *jvals,
+                     ac_stream stream) {
+  if (ac_status s = check_cells(net, n_cells)) return s;
+  if (n_cells && (!y || !T || !dydt || !jvals)) return fail(AC_EINVAL, "null y, T, dydt or jvals");
+  hipError_t e = ac::launch_rhs_jac(net->d, log_alpha, n_cells, y, T, dydt, jvals,
+                                    hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_rhs_jac launch");
+}
+
 ac_status ac_vjp(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *y,
                  const double *T, const double *v, double *gy, double *g_logalpha,
                  ac_stream stream) {

@@ -42,6 +42,8 @@ hipError_t launch_rhs(const DNet &n, const double *log_alpha, int64_t n_cells, c
                       const double *T, const double *k, double *dydt, hipStream_t stream);
 hipError_t launch_jac(const DNet &n, const double *log_alpha, int64_t n_cells, const double *y,
                       const double *T, double *jvals, hipStream_t stream);
+hipError_t launch_rhs_jac(const DNet &n, const double *log_alpha, int64_t n_cells, const double *y,
+                          const double *T, double *dydt, double *jvals, hipStream_t stream);
 hipError_t launch_vjp(const DNet &n, const double *log_alpha, int64_t n_cells, const double *y,
                       const double *T, const double *v, double *gy, double *g_logalpha,
                       double *part, int part_rows, hipStream_t stream);

@@ -218,13 +218,86 @@ __global__ __launch_bounds__(NT) void k_jac(DNet n, const double *__restrict__ l
 // without branching; only the few entries with more tail slots loop. Needs
 // twice the LDS, so one 1024-thread workgroup per CU takes the place of two
 // 512-thread ones.
+// One pass of k_jac2 over the cell pair (c, c+1) (the second absent unless
+// two): densities and coefficients into LDS, tail runs, then every entry
+// written. zslot is the index of the (0, 0) slot pair. Leaves kk (the
+// coefficients) and yy in LDS; the caller places the next barrier.
+template <int NT>
+__device__ __forceinline__ void jac2_pass(const DNet &n, const double *__restrict__ la_over,
+                                          int64_t c, bool two, const double *__restrict__ y,
+                                          const double *__restrict__ T,
+                                          double *__restrict__ jvals, double2 *yy, double2 *kk,
+                                          double2 *pp, uint32_t zslot) {
+  const int ns = n.ns, nr = n.nr, nnz = n.nnz_j;
+  for (int i = threadIdx.x; i < ns; i += NT)
+    yy[i] = make_double2(y[c * ns + i], two ? y[(c + 1) * ns + i] : 0.0);
+  double L0, invT0, L1, invT1;
+  cell_temperature(T[c], L0, invT0);
+  cell_temperature(two ? T[c + 1] : T[c], L1, invT1);
+  for (int j0 = threadIdx.x; j0 < nr; j0 += RXU * NT) {
+    Rx r[RXU];
+#pragma unroll
+    for (int u = 0; u < RXU; ++u) {
+      const int j = j0 + u * NT;
+      if (j < nr) {
+        r[u] = load_rx(n, j);
+        if (la_over) r[u].la = la_over[j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RXU; ++u) {
+      const int j = j0 + u * NT;
+      if (j < nr)
+        kk[j] = make_double2(kooij(r[u].la, r[u].beta, r[u].gamma, L0, invT0),
+                             kooij(r[u].la, r[u].beta, r[u].gamma, L1, invT1));
+    }
+  }
+  __syncthreads();
+  runsum_pairs<NT>(n.jtail, kk, yy, uint32_t(ns), pp);
+  __syncthreads();
+  double *out0 = jvals + c * nnz, *out1 = out0 + nnz;
+  const uint32_t unnz = uint32_t(nnz);
+  constexpr int EU = 4;
+  for (uint32_t e0 = threadIdx.x; e0 < unnz; e0 += EU * NT) {
+    uint32_t h0[EU], h1[EU], td[EU];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      const uint32_t e = e0 + u * NT;
+      const bool ok = e < unnz;
+      h0[u] = ok ? n.jhead0[e] : PAD_ITEM;
+      h1[u] = ok ? n.jhead1[e] : PAD_ITEM;
+      td[u] = ok ? n.jtaildesc[e] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      const uint32_t e = e0 + u * NT;
+      if (e < unnz) {
+        double a0 = 0.0, a1 = 0.0;
+        term_pair(h0[u], kk, yy, uint32_t(ns), a0, a1);
+        term_pair(h1[u], kk, yy, uint32_t(ns), a0, a1);
+        const uint32_t q0 = td[u] >> 8, nq = td[u] & 255u;
+        const double2 p0 = pp[nq > 0u ? q0 : zslot], p1 = pp[nq > 1u ? q0 + 1u : zslot];
+        a0 = __dadd_rn(__dadd_rn(a0, p0.x), p1.x);
+        a1 = __dadd_rn(__dadd_rn(a1, p0.y), p1.y);
+        for (uint32_t q = 2; q < nq; ++q) {
+          const double2 pq = pp[q0 + q];
+          a0 = __dadd_rn(a0, pq.x);
+          a1 = __dadd_rn(a1, pq.y);
+        }
+        __builtin_nontemporal_store(a0, out0 + e);
+        if (two) __builtin_nontemporal_store(a1, out1 + e);
+      }
+    }
+  }
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_jac2(DNet n, const double *__restrict__ la_over,
                                              int64_t n_cells, const double *__restrict__ y,
                                              const double *__restrict__ T,
                                              double *__restrict__ jvals) {
   extern __shared__ double sm[];
-  const int ns = n.ns, nr = n.nr, nnz = n.nnz_j;
+  const int ns = n.ns, nr = n.nr;
   const uint32_t nslot = uint32_t(n.jtail.n_slot > 0 ? n.jtail.n_slot : 0);
   double2 *yy = reinterpret_cast<double2 *>(sm);   // ns + 1
   double2 *kk = yy + ns + 1;                         // nr
@@ -234,67 +307,54 @@ __global__ __launch_bounds__(NT) void k_jac2(DNet n, const double *__restrict__ 
     pp[nslot] = make_double2(0.0, 0.0);
   }
   for (int64_t c = 2 * int64_t(blockIdx.x); c < n_cells; c += 2 * int64_t(gridDim.x)) {
+    jac2_pass<NT>(n, la_over, c, c + 1 < n_cells, y, T, jvals, yy, kk, pp, nslot);
+    __syncthreads();
+  }
+}
+
+// RHS and Jacobian together, two cells per pass (SELL rows of S): the
+// Jacobian pass of k_jac2, then the coefficients in LDS become the rates in
+// place (k_j times the reactant densities, multiplied in k_rhs2's order)
+// and the SELL row sums of k_rhs2 run on them, their partials in the slot
+// region. One coefficient evaluation and one density load serve both
+// outputs; both are bit-identical to k_jac2's and k_rhs2's.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_rhs_jac2(DNet n, const double *__restrict__ la_over,
+                                                 int64_t n_cells, const double *__restrict__ y,
+                                                 const double *__restrict__ T,
+                                                 double *__restrict__ dydt,
+                                                 double *__restrict__ jvals) {
+  extern __shared__ double sm[];
+  const int ns = n.ns, nr = n.nr;
+  const int js = n.jtail.n_slot > 0 ? n.jtail.n_slot : 0, rs = n.rhs.n_slot > 0 ? n.rhs.n_slot : 0;
+  const uint32_t zslot = uint32_t(js > rs ? js : rs);   // beyond both kinds of partials
+  double2 *yy = reinterpret_cast<double2 *>(sm);   // ns + 1
+  double2 *kk = yy + ns + 1;                         // nr
+  double2 *pp = kk + nr;                             // zslot + 1
+  if (threadIdx.x == 0) {
+    yy[ns] = make_double2(1.0, 1.0);
+    pp[zslot] = make_double2(0.0, 0.0);
+  }
+  for (int64_t c = 2 * int64_t(blockIdx.x); c < n_cells; c += 2 * int64_t(gridDim.x)) {
     const bool two = c + 1 < n_cells;
-    for (int i = threadIdx.x; i < ns; i += NT)
-      yy[i] = make_double2(y[c * ns + i], two ? y[(c + 1) * ns + i] : 0.0);
-    double L0, invT0, L1, invT1;
-    cell_temperature(T[c], L0, invT0);
-    cell_temperature(two ? T[c + 1] : T[c], L1, invT1);
-    for (int j0 = threadIdx.x; j0 < nr; j0 += RXU * NT) {
-      Rx r[RXU];
-#pragma unroll
-      for (int u = 0; u < RXU; ++u) {
-        const int j = j0 + u * NT;
-        if (j < nr) {
-          r[u] = load_rx(n, j);
-          if (la_over) r[u].la = la_over[j];
-        }
+    jac2_pass<NT>(n, la_over, c, two, y, T, jvals, yy, kk, pp, zslot);
+    __syncthreads();
+    for (int j = threadIdx.x; j < nr; j += NT) {
+      const uint32_t pair = n.rpair[j];
+      const double2 kv = kk[j], ya = yy[pair & 0xFFFFu];
+      double r0 = kv.x * ya.x, r1 = kv.y * ya.y;
+      if ((pair >> 16) != 0xFFFFu) {
+        const double2 yb = yy[pair >> 16];
+        r0 *= yb.x;
+        r1 *= yb.y;
       }
-#pragma unroll
-      for (int u = 0; u < RXU; ++u) {
-        const int j = j0 + u * NT;
-        if (j < nr)
-          kk[j] = make_double2(kooij(r[u].la, r[u].beta, r[u].gamma, L0, invT0),
-                               kooij(r[u].la, r[u].beta, r[u].gamma, L1, invT1));
-      }
+      kk[j] = make_double2(r0, r1);
     }
     __syncthreads();
-    runsum_pairs<NT>(n.jtail, kk, yy, uint32_t(ns), pp);
+    double *out0 = dydt + c * ns, *out1 = two ? out0 + ns : nullptr;
+    sell_pairs<NT>(n.rhs, kk, nullptr, 0u, pp, out0, out1);
     __syncthreads();
-    double *out0 = jvals + c * nnz, *out1 = out0 + nnz;
-    const uint32_t unnz = uint32_t(nnz);
-    constexpr int EU = 4;
-    for (uint32_t e0 = threadIdx.x; e0 < unnz; e0 += EU * NT) {
-      uint32_t h0[EU], h1[EU], td[EU];
-#pragma unroll
-      for (int u = 0; u < EU; ++u) {
-        const uint32_t e = e0 + u * NT;
-        const bool ok = e < unnz;
-        h0[u] = ok ? n.jhead0[e] : PAD_ITEM;
-        h1[u] = ok ? n.jhead1[e] : PAD_ITEM;
-        td[u] = ok ? n.jtaildesc[e] : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < EU; ++u) {
-        const uint32_t e = e0 + u * NT;
-        if (e < unnz) {
-          double a0 = 0.0, a1 = 0.0;
-          term_pair(h0[u], kk, yy, uint32_t(ns), a0, a1);
-          term_pair(h1[u], kk, yy, uint32_t(ns), a0, a1);
-          const uint32_t q0 = td[u] >> 8, nq = td[u] & 255u;
-          const double2 p0 = pp[nq > 0u ? q0 : nslot], p1 = pp[nq > 1u ? q0 + 1u : nslot];
-          a0 = __dadd_rn(__dadd_rn(a0, p0.x), p1.x);
-          a1 = __dadd_rn(__dadd_rn(a1, p0.y), p1.y);
-          for (uint32_t q = 2; q < nq; ++q) {
-            const double2 pq = pp[q0 + q];
-            a0 = __dadd_rn(a0, pq.x);
-            a1 = __dadd_rn(a1, pq.y);
-          }
-          __builtin_nontemporal_store(a0, out0 + e);
-          if (two) __builtin_nontemporal_store(a1, out1 + e);
-        }
-      }
-    }
+    segsum_finish_pairs<NT>(n.rhs, pp, out0, out1);
     __syncthreads();
   }
 }
@@ -563,6 +623,24 @@ static hipError_t jac_nt(const DNet &n, const double *la, int64_t n_cells, const
   const int g = grid_for(k_jac<NT>, NT, lds, n_cells);
   hipLaunchKernelGGL(k_jac<NT>, dim3(g), dim3(NT), lds, st, n, la, n_cells, y, T, jvals);
   return hipGetLastError();
+}
+
+// RHS + Jacobian in one pass per cell pair when the layout is SELL with
+// fused coefficients and the pair's LDS fits; otherwise the two launches.
+hipError_t launch_rhs_jac(const DNet &n, const double *la, int64_t n_cells, const double *y,
+                          const double *T, double *dydt, double *jvals, hipStream_t st) {
+  if (n_cells == 0) return hipSuccess;
+  const int js = n.jtail.n_slot > 0 ? n.jtail.n_slot : 0, rs = n.rhs.n_slot > 0 ? n.rhs.n_slot : 0;
+  const size_t lds2 = 2 * sizeof(double) * size_t(n.ns + 1 + n.nr + (js > rs ? js : rs) + 1);
+  if (n.layout == LAYOUT_SELL && n_cells > 1 && lds2 <= 160 * 1024) {
+    const int g = grid_for(k_rhs_jac2<1024>, 1024, lds2, (n_cells + 1) / 2);
+    hipLaunchKernelGGL(k_rhs_jac2<1024>, dim3(g), dim3(1024), lds2, st, n, la, n_cells, y, T,
+                       dydt, jvals);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_rhs(n, la, n_cells, y, T, nullptr, dydt, st);
+  if (e != hipSuccess) return e;
+  return launch_jac(n, la, n_cells, y, T, jvals, st);
 }
 
 hipError_t launch_jac(const DNet &n, const double *la, int64_t n_cells, const double *y,

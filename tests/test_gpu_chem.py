@@ -253,3 +253,20 @@ def test_two_cell_kernels_independent_of_partner(acm, torch_dev, medium_net, med
     ga, _ = N.vjp(*a)
     gb, _ = N.vjp(*b)
     assert np.array_equal(ga.cpu().numpy()[1:7], gb.cpu().numpy()[0:6])
+
+
+@pytest.mark.parametrize("n_cells", [1, 2, 7, 64])
+def test_rhs_jac_fused_equals_separate(acm, torch_dev, medium_net, med_cells, n_cells):
+    """ac_rhs_jac (one kernel for both outputs with SELL) is bit-identical to
+    ac_rhs followed by ac_jac, including a lone last cell and one cell."""
+    torch = torch_dev
+    for layout in ("sell", "csr"):
+        N = acm.Network.from_synth(medium_net, layout=layout)
+        y, T = _t(torch, med_cells.y0[:n_cells]), _t(torch, med_cells.T[:n_cells])
+        d1 = torch.empty_like(y)
+        j1 = torch.empty((n_cells, N.nnz_j), dtype=torch.float64, device="cuda")
+        d2, j2 = torch.empty_like(d1), torch.empty_like(j1)
+        acm.ac_rhs(N, None, y, T, d1)
+        acm.ac_jac(N, None, y, T, j1)
+        acm.ac_rhs_jac(N, None, y, T, d2, j2)
+        assert torch.equal(d1, d2) and torch.equal(j1, j2), layout
