@@ -5,15 +5,15 @@ layout of S (CRS chunks, SELL-C-sigma, equal runs, COO, CCS), the species
 traversal order (natural, nnz-descending, reverse Cuthill-McKee) and the
 workgroup size (256, 512 or 1024 threads). Which combination is fastest
 depends on the network's shape and on the cell count, so `autotune` times
-every candidate on the caller's own cells (RHS + Jacobian, HIP events on
-the current stream) and returns the network built with the winner.
+every candidate on the caller's own cells (ac_rhs_jac, the RHS and the
+Jacobian together, HIP events on the current stream) and returns the network built with the winner.
 """
 from __future__ import annotations
 
 import itertools
 from typing import Dict, Iterable, Tuple
 
-from . import Network, ac_jac, ac_rhs
+from . import Network, ac_rhs, ac_rhs_jac
 
 LAYOUTS = ("sell", "csr", "runs", "coo", "ccs")
 ORDERINGS = ("nnz", "natural", "rcm")
@@ -35,7 +35,7 @@ def _time_ms(torch, fn, reps: int) -> float:
 def autotune(net, y, T, layouts: Iterable[str] = LAYOUTS, orderings: Iterable[str] = ORDERINGS,
              blocks: Iterable[int] = BLOCKS, reps: int = 3, with_jac: bool = True
              ) -> Tuple[Network, Dict[str, object], Dict[Tuple[str, str, int], float]]:
-    """Times ac_rhs (+ ac_jac) for every (layout, ordering, block) on the
+    """Times ac_rhs_jac (ac_rhs alone without with_jac) for every (layout, ordering, block) on the
     device tensors y [cells, ns] and T [cells]; returns (network built with
     the fastest choice, its keyword arguments, table of ms per step)."""
     import torch
@@ -49,9 +49,10 @@ def autotune(net, y, T, layouts: Iterable[str] = LAYOUTS, orderings: Iterable[st
             jv = torch.empty((y.shape[0], N.nnz_j), dtype=torch.float64, device=y.device)
 
         def step():
-            ac_rhs(N, None, y, T, dydt)
             if with_jac:
-                ac_jac(N, None, y, T, jv)
+                ac_rhs_jac(N, None, y, T, dydt, jv)
+            else:
+                ac_rhs(N, None, y, T, dydt)
 
         table[(lay, order, blk)] = _time_ms(torch, step, reps)
         N.close()
