@@ -180,8 +180,9 @@ ac_status ac_rhs_k(const ac_net *net, int64_t n_cells, const double *k, const do
 ac_status ac_jac(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *y,
                  const double *T, double *jvals, ac_stream stream);
 
-/* ac_rhs and ac_jac in one call: dydt [n_cells][n_species] and jvals
- * [n_cells][nnz_j], bit-identical to the two calls. With the SELL layout
+/* ac_rhs and ac_jac in one call (eq. matrix-form and its Jacobian, Sec.
+ * 2.1): dydt [n_cells][n_species] and jvals [n_cells][nnz_j], DEVICE,
+ * written; bit-identical to the two calls. With the SELL layout
  * one kernel computes the coefficients once per cell for both (the
  * Newton step needs both at the same state); otherwise it issues the two
  * launches. Errors as ac_rhs / ac_jac. */
