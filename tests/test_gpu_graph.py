@@ -1,6 +1,6 @@
 """Capture of the hot path in a HIP graph: the library's calls allocate
-nothing and clear their device queue with a kernel, so rhs, jac and the
-persistent integrator can be recorded once and replayed. Every replay,
+nothing and clear their device queue with a kernel, so rhs, jac, the fused
+rhs_jac and the persistent integrator can be recorded once and replayed. Every replay,
 with eager work and synchronisations in between, must reproduce the eager
 result bit for bit."""
 import numpy as np
@@ -45,6 +45,8 @@ def test_graph_replays_integration(acm, torch_dev, which):
     y = y0.clone()
     f = torch.empty_like(y0)
     jv = torch.empty_like(j_ref)
+    f2 = torch.empty_like(y0)                       # the fused call's outputs
+    jv2 = torch.empty_like(j_ref)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):                      # warm-up on the capture stream
@@ -57,15 +59,19 @@ def test_graph_replays_integration(acm, torch_dev, which):
         y.copy_(y0)
         acm.ac_rhs(N, None, y0, T, f)
         acm.ac_jac(N, None, y0, T, jv)
+        acm.ac_rhs_jac(N, None, y0, T, f2, jv2)
         out = ws.integrate(y, T, t_end)
     for rep in range(3):
         y.fill_(-1.0)
         f.zero_()
         jv.zero_()
+        f2.zero_()
+        jv2.zero_()
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(f, f_ref) and torch.equal(jv, j_ref), rep
+        assert torch.equal(f2, f_ref) and torch.equal(jv2, j_ref), rep
         assert torch.equal(y, y_ref), rep
         assert torch.equal(out["stats"], o_ref["stats"]) and torch.equal(out["status"], o_ref["status"])
         # eager work between replays
