@@ -17,6 +17,10 @@
  *    by cell ([n_cells][n_species], each cell contiguous, species in the
  *    natural order of the network description). Orderings chosen at network
  *    creation only change the traversal inside the kernels.
+ *  - The argument named T is the per-cell conditions array: [n_cells]
+ *    temperatures [K] for a network whose reactions all follow the modified
+ *    Arrhenius law (rate_law NULL at creation), else [n_cells][AC_NCOND]
+ *    rows (T [K], A_V [mag], zeta/zeta_0, G_0), see ac_rate_law.
  *  - Work is enqueued on `stream` (a hipStream_t; NULL is the null stream)
  *    and the call returns without synchronising. Argument errors are found
  *    on the host before anything is enqueued.
@@ -86,6 +90,21 @@ typedef enum {
   AC_ORDER_RCM = 2        /* reverse Cuthill-McKee on the species graph of S S^T */
 } ac_ordering;
 
+/* Rate laws. The coefficients depend on local conditions: temperature,
+ * cosmic-ray ionisation rate and FUV intensity (Sec. 3). With per-cell
+ * conditions (T, A_V, zeta/zeta_0, G_0):
+ *   AC_LAW_KOOIJ   k = alpha (T/300)^beta exp(-gamma/T)         (modified Arrhenius)
+ *   AC_LAW_CRP     k = alpha zeta/zeta_0                        (direct cosmic-ray ionisation;
+ *                                                                beta, gamma unused)
+ *   AC_LAW_CRPHOT  k = alpha (T/300)^beta gamma zeta/zeta_0 / (1 - AC_GRAIN_ALBEDO)
+ *                                                               (cosmic-ray induced photons;
+ *                                                                gamma: efficiency, > 0)
+ *   AC_LAW_PHOTO   k = alpha G_0 exp(-gamma A_V)                (interstellar FUV; beta unused)
+ * Every law is linear in alpha, so d k / d ln alpha = k for all of them. */
+typedef enum { AC_LAW_KOOIJ = 0, AC_LAW_CRP = 1, AC_LAW_CRPHOT = 2, AC_LAW_PHOTO = 3 } ac_rate_law;
+#define AC_NCOND 4
+#define AC_GRAIN_ALBEDO 0.6
+
 #define AC_MAX_SPECIES 2047
 #define AC_MAX_REACTIONS 65536
 #define AC_MAX_REACTANTS 2
@@ -110,6 +129,8 @@ typedef struct {
   int32_t sell_sigma;        /* SELL sorting window in chunks; 0 = default (whole matrix) */
   int32_t block;             /* threads per workgroup of the chemistry kernels: 256, 512
                                 or 1024; 0 = default (512) */
+  const int8_t *rate_law;    /* host [n_reactions] ac_rate_law codes, or NULL (every reaction
+                                AC_LAW_KOOIJ, per-cell conditions = T only) */
 } ac_net_desc;
 
 typedef struct ac_net ac_net;
@@ -160,8 +181,10 @@ ac_status ac_sparse_format(int32_t n_rows, int32_t n_cols, const int32_t *dense,
  * log_alpha: optional DEVICE [n_reactions] override of ln(alpha) (for
  * differentiation); NULL uses the network's own coefficients. */
 
-/* k[c][j] = alpha_j (T_c/300)^beta_j exp(-gamma_j/T_c), the coefficients the
- * paper precomputes outside the stiff solver (Sec. 3). k: [n_cells][n_reactions]. */
+/* k[c][j] = the coefficient of reaction j by its rate law at cell c's
+ * conditions (alpha_j (T_c/300)^beta_j exp(-gamma_j/T_c) for the default
+ * law), the coefficients the paper precomputes outside the stiff solver
+ * (Sec. 3). k: [n_cells][n_reactions]. */
 ac_status ac_rates(const ac_net *net, const double *log_alpha, int64_t n_cells, const double *T,
                    double *k, ac_stream stream);
 
@@ -325,7 +348,20 @@ ac_status ac_integrate_adjoint(ac_ws *ws, const double *log_alpha, int64_t n_cel
                                double *g_cells, double *dL_dlogalpha, int32_t *cell_status,
                                int32_t *cell_stats, ac_stream stream);
 
-/* Status text and the calling thread's last error message (incl. HIP's). */
+/* The forward half of ac_integrate_adjoint alone: replays a recorded step
+ * sequence (as written by ac_integrate) from y0 with every corrector
+ * equation solved to convergence and writes the replayed y(t_end) to
+ * y_final [n_cells][n_species] (DEVICE). Step sizes, orders and
+ * resamplings come from the tape, so the result is a smooth function of y0
+ * and log_alpha (what finite differences of the adjoint's map need).
+ * cell_status / cell_stats as for ac_integrate_adjoint (either may be
+ * NULL). Errors: AC_EINVAL for bad sizes or NULL required arrays. */
+ac_status ac_replay(ac_ws *ws, const double *log_alpha, int64_t n_cells, const double *y0,
+                    const double *T, const ac_integ_opts *opts, const ac_event *tape,
+                    int32_t tape_cap, const int32_t *tape_len, double *y_final,
+                    int32_t *cell_status, int32_t *cell_stats, ac_stream stream);
+
+/* Status text and the calling thread's last error message (incl. HIP's). *//* Status text and the calling thread's last error message (incl. HIP's). */
 const char *ac_status_string(ac_status s);
 int ac_last_error(char *buf, size_t n);
 

@@ -37,7 +37,14 @@ def build(force: bool = True) -> str:
 class _Net(C.Structure):
     _fields_ = [("n_species", C.c_int), ("n_reactions", C.c_int),
                 ("reactants", C.c_void_p), ("products", C.c_void_p),
-                ("alpha", C.c_void_p), ("beta", C.c_void_p), ("gamma", C.c_void_p)]
+                ("alpha", C.c_void_p), ("beta", C.c_void_p), ("gamma", C.c_void_p),
+                ("law", C.c_void_p), ("n_cond", C.c_int)]
+
+
+# Rate laws (oracle.h) and the per-cell conditions they read: (T, A_V,
+# zeta/zeta_0, G_0).
+LAW_KOOIJ, LAW_CRP, LAW_CRPHOT, LAW_PHOTO = 0, 1, 2, 3
+NCOND = 4
 
 
 class _Opts(C.Structure):
@@ -108,8 +115,11 @@ class NetView:
             else int(net.n_species)
         self.nr = int(self.reactants.shape[0])
         assert self.reactants.shape == (self.nr, 2) and self.products.shape == (self.nr, 4)
+        law = getattr(net, "law", None)
+        self.law = None if law is None else np.ascontiguousarray(law, np.int8)
+        self.n_cond = NCOND if self.law is not None else 1
         self.s = _Net(self.ns, self.nr, _p(self.reactants), _p(self.products),
-                      _p(self.alpha), _p(self.beta), _p(self.gamma))
+                      _p(self.alpha), _p(self.beta), _p(self.gamma), _p(self.law), self.n_cond)
 
     @property
     def ptr(self):
@@ -125,6 +135,18 @@ def _cells(a, n: int) -> np.ndarray:
     return a.reshape(-1, n)
 
 
+def _cond(v: NetView, T) -> np.ndarray:
+    """Per-cell conditions: T [n] for an all-Kooij network, [n, NCOND] rows
+    (T, A_V, zeta/zeta_0, G_0) when the network has rate laws."""
+    T = _f64(T)
+    if v.n_cond == 1:
+        return _f64(np.atleast_1d(T).reshape(-1))
+    T = np.atleast_2d(T)
+    if T.shape[1] != v.n_cond:
+        raise ValueError(f"conditions need {v.n_cond} values per cell, got shape {T.shape}")
+    return np.ascontiguousarray(T)
+
+
 def stoich(net) -> np.ndarray:
     v = _view(net)
     S = np.zeros((v.ns, v.nr), np.int32)
@@ -134,16 +156,16 @@ def stoich(net) -> np.ndarray:
 
 def rate_coeffs(net, T) -> np.ndarray:
     v = _view(net)
-    T = _f64(np.atleast_1d(T))
-    k = np.zeros((T.size, v.nr))
-    lib().orc_rate_coeffs(v.ptr, T.size, _p(T), _p(k))
+    T = _cond(v, T)
+    k = np.zeros((T.shape[0], v.nr))
+    lib().orc_rate_coeffs(v.ptr, T.shape[0], _p(T), _p(k))
     return k
 
 
 def rates(net, y, T) -> np.ndarray:
     v = _view(net)
     y = _cells(y, v.ns)
-    T = _f64(np.atleast_1d(T))
+    T = _cond(v, T)
     r = np.zeros((y.shape[0], v.nr))
     lib().orc_rates(v.ptr, y.shape[0], _p(y), _p(T), _p(r))
     return r
@@ -152,7 +174,7 @@ def rates(net, y, T) -> np.ndarray:
 def rhs(net, y, T, with_abs: bool = False):
     v = _view(net)
     y = _cells(y, v.ns)
-    T = _f64(np.atleast_1d(T))
+    T = _cond(v, T)
     out = np.zeros_like(y)
     ab = np.zeros_like(y) if with_abs else None
     lib().orc_rhs(v.ptr, y.shape[0], _p(y), _p(T), _p(out), _p(ab))
@@ -172,7 +194,7 @@ def rhs_k(net, k, y, with_abs: bool = False):
 def jac_dense(net, y, T, with_abs: bool = False):
     v = _view(net)
     y = _cells(y, v.ns)
-    T = _f64(np.atleast_1d(T))
+    T = _cond(v, T)
     J = np.zeros((y.shape[0], v.ns, v.ns))
     ab = np.zeros_like(J) if with_abs else None
     lib().orc_jac_dense(v.ptr, y.shape[0], _p(y), _p(T), _p(J), _p(ab))
@@ -183,7 +205,7 @@ def vjp(net, y, T, vec):
     v = _view(net)
     y = _cells(y, v.ns)
     vec = _cells(vec, v.ns)
-    T = _f64(np.atleast_1d(T))
+    T = _cond(v, T)
     gy = np.zeros_like(y)
     gl = np.zeros((y.shape[0], v.nr))
     lib().orc_vjp(v.ptr, y.shape[0], _p(y), _p(T), _p(vec), _p(gy), _p(gl))
@@ -217,7 +239,7 @@ def bdf(net, y0, T, t_end, rtol=1e-6, atol=1e-20, q_max=5, max_steps=100000, h0=
     if tape_cap > 0, the recorded step sequence (tape, tape_len)."""
     v = _view(net)
     y = np.array(_cells(y0, v.ns), copy=True)
-    T = _f64(np.atleast_1d(T))
+    T = _cond(v, T)
     n = y.shape[0]
     status = np.zeros(n, np.int32)
     stats = np.zeros((n, len(STAT_NAMES)), np.int32)
@@ -240,7 +262,7 @@ def bdf_replay(net, y0, T, tape, tape_len, rtol=1e-6, atol=1e-20, dy0=None, dlog
     dlogalpha [n_dir, nr]). Returns (y [cells, ns], s [cells, n_dir, ns])."""
     v = _view(net)
     y0 = _cells(y0, v.ns)
-    T = _f64(np.atleast_1d(T))
+    T = _cond(v, T)
     n = y0.shape[0]
     tape = np.ascontiguousarray(tape, EVENT_DTYPE)
     tape_len = np.ascontiguousarray(tape_len, np.int32)

@@ -52,15 +52,32 @@ void orc_stoich(const orc_net *net, int *S) {
 
 /* ------------------------------------------------------- rates and RHS */
 
-/* Modified Arrhenius (Kooij) coefficient, held fixed at the cell's
- * temperature (the coefficients are precomputed outside the stiff solver,
- * Sec. 3; temperature is constant during the chemistry update, Sec. 5). */
-static double rate_coeff(const orc_net *net, int j, double T) {
-  return net->alpha[j] * pow(T / 300.0, net->beta[j]) * exp(-net->gamma[j] / T);
+static int n_cond(const orc_net *net) { return net->n_cond > 1 ? net->n_cond : 1; }
+
+/* Rate coefficient of reaction j at a cell's conditions c = (T, A_V,
+ * zeta/zeta_0, G_0), held fixed during the chemistry update (the
+ * coefficients are precomputed outside the stiff solver and depend on the
+ * temperature, the cosmic-ray ionisation rate and the FUV intensity, Sec.
+ * 3; temperature is constant during the update, Sec. 5). The default law
+ * is the modified Arrhenius (Kooij) form. */
+static double rate_coeff(const orc_net *net, int j, const double *c) {
+  const int law = net->law ? net->law[j] : ORC_LAW_KOOIJ;
+  const double T = c[0];
+  switch (law) {
+    case ORC_LAW_CRP:
+      return net->alpha[j] * c[2];
+    case ORC_LAW_CRPHOT:
+      return net->alpha[j] * pow(T / 300.0, net->beta[j]) * net->gamma[j] * c[2] /
+             (1.0 - ORC_GRAIN_ALBEDO);
+    case ORC_LAW_PHOTO:
+      return net->alpha[j] * c[3] * exp(-net->gamma[j] * c[1]);
+    default:
+      return net->alpha[j] * pow(T / 300.0, net->beta[j]) * exp(-net->gamma[j] / T);
+  }
 }
 
-static void cell_rate_coeffs(const orc_net *net, double T, double *k) {
-  for (int j = 0; j < net->n_reactions; ++j) k[j] = rate_coeff(net, j, T);
+static void cell_rate_coeffs(const orc_net *net, const double *c, double *k) {
+  for (int j = 0; j < net->n_reactions; ++j) k[j] = rate_coeff(net, j, c);
 }
 
 /* R_j of eq. (matrix-form): the coefficient times the density of every
@@ -103,7 +120,7 @@ static void cell_rhs_k(const orc_net *net, const double *k, const double *y, dou
 void orc_rate_coeffs(const orc_net *net, long n_cells, const double *T, double *k) {
   const int nr = net->n_reactions;
 #pragma omp parallel for num_threads(g_threads) schedule(static)
-  for (long c = 0; c < n_cells; ++c) cell_rate_coeffs(net, T[c], k + (size_t)c * nr);
+  for (long c = 0; c < n_cells; ++c) cell_rate_coeffs(net, T + (size_t)c * n_cond(net), k + (size_t)c * nr);
 }
 
 void orc_rates(const orc_net *net, long n_cells, const double *y, const double *T, double *r) {
@@ -113,7 +130,7 @@ void orc_rates(const orc_net *net, long n_cells, const double *y, const double *
     double *k = xcalloc((size_t)nr, sizeof(double));
 #pragma omp for schedule(static)
     for (long c = 0; c < n_cells; ++c) {
-      cell_rate_coeffs(net, T[c], k);
+      cell_rate_coeffs(net, T + (size_t)c * n_cond(net), k);
       for (int j = 0; j < nr; ++j)
         r[(size_t)c * nr + j] = reaction_rate(net, k, y + (size_t)c * ns, j);
     }
@@ -129,7 +146,7 @@ void orc_rhs(const orc_net *net, long n_cells, const double *y, const double *T,
     double *k = xcalloc((size_t)nr, sizeof(double));
 #pragma omp for schedule(static)
     for (long c = 0; c < n_cells; ++c) {
-      cell_rate_coeffs(net, T[c], k);
+      cell_rate_coeffs(net, T + (size_t)c * n_cond(net), k);
       cell_rhs_k(net, k, y + (size_t)c * ns, dydt + (size_t)c * ns,
                  absterm ? absterm + (size_t)c * ns : NULL);
     }
@@ -199,7 +216,7 @@ void orc_jac_dense(const orc_net *net, long n_cells, const double *y, const doub
     double *k = xcalloc((size_t)nr, sizeof(double));
 #pragma omp for schedule(static)
     for (long c = 0; c < n_cells; ++c) {
-      cell_rate_coeffs(net, T[c], k);
+      cell_rate_coeffs(net, T + (size_t)c * n_cond(net), k);
       cell_jac(net, k, y + (size_t)c * ns, J + (size_t)c * nn, absJ ? absJ + (size_t)c * nn : NULL);
     }
     free(k);
@@ -248,7 +265,7 @@ void orc_vjp(const orc_net *net, long n_cells, const double *y, const double *T,
     double *k = xcalloc((size_t)nr, sizeof(double));
 #pragma omp for schedule(static)
     for (long c = 0; c < n_cells; ++c) {
-      cell_rate_coeffs(net, T[c], k);
+      cell_rate_coeffs(net, T + (size_t)c * n_cond(net), k);
       cell_vjp(net, k, y + (size_t)c * ns, v + (size_t)c * ns, gy ? gy + (size_t)c * ns : NULL,
                glog ? glog + (size_t)c * nr : NULL);
     }
@@ -259,7 +276,11 @@ void orc_vjp(const orc_net *net, long n_cells, const double *y, const double *T,
 /* ------------------------------------------------------------------ LU */
 
 /* Doolittle elimination with partial (row) pivoting; whole rows are swapped
- * so that P A = L U holds for the final factors. */
+ * so that P A = L U holds for the final factors. The row update is an
+ * element-wise loop, so the AVX2 clone (picked at load time where the CPU
+ * has it) rounds every element exactly as the plain one does: no
+ * contraction, no reassociation. */
+__attribute__((target_clones("avx2", "default")))
 int orc_lu_factor(int n, double *A, int *piv) {
   int info = 0;
   for (int k = 0; k < n; ++k) {
@@ -546,17 +567,19 @@ static void tape_put(tape_w *t, int type, int q, double val) {
   t->len++;
 }
 
-static int valid_input(int n, const double *y, double T) {
-  if (!(isfinite(T) && T > 0.0)) return 0;
+static int valid_input(int n, const double *y, const double *cond, int nc) {
+  if (!(isfinite(cond[0]) && cond[0] > 0.0)) return 0;
+  for (int i = 1; i < nc; ++i)
+    if (!(isfinite(cond[i]) && cond[i] >= 0.0)) return 0;
   for (int i = 0; i < n; ++i)
     if (!(isfinite(y[i]) && y[i] >= 0.0)) return 0;
   return 1;
 }
 
-static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, double T, double t_end,
-                    int *st, tape_w *tw) {
+static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, const double *cond,
+                    double t_end, int *st, tape_w *tw) {
   const int n = net->n_species, nr = net->n_reactions;
-  if (!valid_input(n, y, T)) return ORC_BADINPUT;
+  if (!valid_input(n, y, cond, n_cond(net))) return ORC_BADINPUT;
   if (!(t_end > 0.0)) return ORC_OK;
   bdf_consts K;
   bdf_constants(&K);
@@ -577,7 +600,7 @@ static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, double
   double *f = xcalloc((size_t)n, sizeof(double));
   double *dy = xcalloc((size_t)n, sizeof(double));
 
-  cell_rate_coeffs(net, T, k);
+  cell_rate_coeffs(net, cond, k);
   cell_ctx cx = {net, k, n, st};
   F(&cx, y, f);
   double h = o->h0 > 0.0 ? fmin(o->h0, t_end) : initial_step(&cx, y, f, rtol, atol, t_end);
@@ -703,7 +726,7 @@ void orc_bdf(const orc_net *net, const orc_bdf_opts *opt, long n_cells, double *
     int *st = stats ? stats + (size_t)c * ORC_NSTAT : NULL;
     if (st) memset(st, 0, sizeof(int) * ORC_NSTAT);
     tape_w tw = {tape ? tape + (size_t)c * tape_cap : NULL, tape_cap, 0, 0};
-    int s = bdf_cell(net, opt, y + (size_t)c * ns, T[c], t_end, st, &tw);
+    int s = bdf_cell(net, opt, y + (size_t)c * ns, T + (size_t)c * n_cond(net), t_end, st, &tw);
     if (status) status[c] = s;
     if (tape_len) tape_len[c] = tw.overflow ? -1 : tw.len;
   }
@@ -742,7 +765,8 @@ static void matvec(int n, const double *A, const double *x, double *out) {
  * the corrector equation is solved to convergence, so the result is a smooth
  * function of the initial state and parameters. Tangents follow from
  * differentiating each step:  (I - c J(y)) s_d = c (J(y) s_pred + f_p) - s_psi. */
-static void replay_cell(const orc_net *net, const orc_bdf_opts *o, const double *y0, double T,
+static void replay_cell(const orc_net *net, const orc_bdf_opts *o, const double *y0,
+                        const double *cond,
                         const orc_event *ev, int n_ev, int n_dir, const double *dy0,
                         const double *dlogalpha, double *y_out, double *s_out) {
   const int n = net->n_species, nr = net->n_reactions;
@@ -765,7 +789,7 @@ static void replay_cell(const orc_net *net, const orc_bdf_opts *o, const double 
   double *t2 = xcalloc((size_t)n, sizeof(double));
   double *sd = xcalloc((size_t)n, sizeof(double));
 
-  cell_rate_coeffs(net, T, k);
+  cell_rate_coeffs(net, cond, k);
   cell_ctx cx = {net, k, n, NULL};
   memcpy(D, y0, sizeof(double) * n);
   for (int r = 0; r < n_dir; ++r)
@@ -865,7 +889,7 @@ void orc_bdf_replay(const orc_net *net, const orc_bdf_opts *opt, long n_cells, c
   const int ns = net->n_species;
 #pragma omp parallel for num_threads(g_threads) schedule(dynamic, 1)
   for (long c = 0; c < n_cells; ++c)
-    replay_cell(net, opt, y0 + (size_t)c * ns, T[c], tape + (size_t)c * tape_cap, tape_len[c],
+    replay_cell(net, opt, y0 + (size_t)c * ns, T + (size_t)c * n_cond(net), tape + (size_t)c * tape_cap, tape_len[c],
                 n_dir, dy0 ? dy0 + (size_t)c * n_dir * ns : NULL, dlogalpha,
                 y_out + (size_t)c * ns, s_out ? s_out + (size_t)c * n_dir * ns : NULL);
 }

@@ -24,7 +24,22 @@ typedef struct {
   const double *alpha;    /* [n_reactions] */
   const double *beta;     /* [n_reactions] */
   const double *gamma;    /* [n_reactions] */
+  const signed char *law; /* [n_reactions] ORC_LAW_*, or NULL: every reaction ORC_LAW_KOOIJ */
+  int n_cond;             /* doubles of per-cell conditions: 1 (T) or ORC_NCOND (T, A_V,
+                             zeta/zeta_0, G_0); 0 is taken as 1 */
 } orc_net;
+
+/* Rate laws (the coefficients depend on the temperature, the cosmic-ray
+ * ionisation rate and the FUV intensity, Sec. 3). Per-cell conditions
+ * cond[c] = (T [K], A_V [mag], zeta/zeta_0, G_0):
+ *   KOOIJ   k = alpha (T/300)^beta exp(-gamma/T)
+ *   CRP     k = alpha zeta/zeta_0                       (direct cosmic-ray ionisation)
+ *   CRPHOT  k = alpha (T/300)^beta gamma zeta/zeta_0 / (1 - omega), omega = 0.6
+ *                                                       (cosmic-ray induced photons)
+ *   PHOTO   k = alpha G_0 exp(-gamma A_V)               (interstellar FUV field) */
+enum { ORC_LAW_KOOIJ = 0, ORC_LAW_CRP = 1, ORC_LAW_CRPHOT = 2, ORC_LAW_PHOTO = 3 };
+#define ORC_NCOND 4
+#define ORC_GRAIN_ALBEDO 0.6
 
 /* Threads used by the per-cell loops (cells are independent). */
 void orc_set_threads(int n);
@@ -34,7 +49,9 @@ int  orc_get_threads(void);
  * reactants) of reaction j (the matrix form of the rate equations, Sec. 2.1). */
 void orc_stoich(const orc_net *net, int *S);
 
-/* k[c][j] = alpha_j (T_c/300)^beta_j exp(-gamma_j/T_c). */
+/* k[c][j] by the reaction's rate law at the cell's conditions. Every "T"
+ * argument below is the per-cell conditions array, n_cond doubles per cell
+ * (just T for an all-KOOIJ network). */
 void orc_rate_coeffs(const orc_net *net, long n_cells, const double *T, double *k);
 
 /* r[c][j] = k_j * product of the reactant densities. */

@@ -40,7 +40,13 @@ class NetDesc(C.Structure):
                 ("composition", C.c_void_p), ("n_elem", C.c_int32),
                 ("check_balance", C.c_int32), ("layout", C.c_int32), ("ordering", C.c_int32),
                 ("chunk", C.c_int32), ("sell_c", C.c_int32), ("sell_sigma", C.c_int32),
-                ("block", C.c_int32)]
+                ("block", C.c_int32), ("rate_law", C.c_void_p)]
+
+
+# Rate laws (ac_rate_law) and the per-cell conditions of a network that has
+# them: rows (T, A_V, zeta/zeta_0, G_0).
+AC_LAW_KOOIJ, AC_LAW_CRP, AC_LAW_CRPHOT, AC_LAW_PHOTO = 0, 1, 2, 3
+AC_NCOND = 4
 
 
 def _load() -> C.CDLL:
@@ -82,6 +88,7 @@ def _load() -> C.CDLL:
         "ac_integrate_plain": [vp, vp, i64, vp, vp, d, vp, vp, vp, vp],
         "ac_integrate_adjoint": [vp, vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
                                  vp, vp],
+        "ac_replay": [vp, vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp],
     }
     for name, args in sig2.items():
         f = getattr(L, name)
@@ -148,13 +155,16 @@ class Network:
 
     def __init__(self, reactants, products, alpha, beta, gamma, composition=None,
                  layout: str = "sell", ordering: str = "nnz", chunk: int = 0, sell_c: int = 0,
-                 sell_sigma: int = 0, check_balance: bool = False, block: int = 0):
+                 sell_sigma: int = 0, check_balance: bool = False, block: int = 0,
+                 rate_law=None):
         self._rea = np.ascontiguousarray(reactants, np.int32)
         self._pro = np.ascontiguousarray(products, np.int32)
         self._a = np.ascontiguousarray(alpha, np.float64)
         self._b = np.ascontiguousarray(beta, np.float64)
         self._g = np.ascontiguousarray(gamma, np.float64)
         self._comp = None if composition is None else np.ascontiguousarray(composition, np.int8)
+        self._law = None if rate_law is None else np.ascontiguousarray(rate_law, np.int8)
+        self.n_cond = 1 if self._law is None else AC_NCOND
         self.n_reactions = int(self._rea.shape[0])
         if composition is not None:
             self.n_species = int(self._comp.shape[0])
@@ -164,7 +174,8 @@ class Network:
         d = NetDesc(self.n_species, self.n_reactions, _ptr(self._rea), _ptr(self._pro),
                     _ptr(self._a), _ptr(self._b), _ptr(self._g), _ptr(self._comp),
                     0 if self._comp is None else self._comp.shape[1], int(check_balance),
-                    LAYOUTS[layout], ORDERINGS[ordering], chunk, sell_c, sell_sigma, block)
+                    LAYOUTS[layout], ORDERINGS[ordering], chunk, sell_c, sell_sigma, block,
+                    _ptr(self._law))
         h = C.c_void_p()
         check(lib.ac_net_create(C.byref(d), C.byref(h)), "ac_net_create")
         self.handle = h
@@ -177,7 +188,11 @@ class Network:
     @classmethod
     def from_synth(cls, net, **kw):
         return cls(net.reactants, net.products, net.alpha, net.beta, net.gamma,
-                   composition=net.composition, **kw)
+                   composition=net.composition, rate_law=getattr(net, "law", None), **kw)
+
+    def cond_shape(self, n: int):
+        """Shape of the per-cell conditions array T for n cells."""
+        return (n,) if self.n_cond == 1 else (n, self.n_cond)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -247,7 +262,7 @@ class Network:
 
 def _cells(net: Network, y, T):
     n = T.shape[0]
-    _check_dev(T, (n,), "T")
+    _check_dev(T, net.cond_shape(n), "T")
     if y is not None:
         _check_dev(y, (n, net.n_species), "y")
     return n
@@ -373,7 +388,7 @@ class Workspace:
         recorded steps (tape [n, tape_cap] of EVENT_DTYPE bytes, tape_len)."""
         import torch
         n = T.shape[0]
-        _check_dev(T, (n,), "T")
+        _check_dev(T, self.net.cond_shape(n), "T")
         _check_dev(y, (n, self.net.n_species), "y")
         if log_alpha is not None:
             _check_dev(log_alpha, (self.net.n_reactions,), "log_alpha")
@@ -411,7 +426,7 @@ class Workspace:
         keeping every converged state (same results, less memory)."""
         import torch
         n, ns, nr = T.shape[0], self.net.n_species, self.net.n_reactions
-        _check_dev(T, (n,), "T")
+        _check_dev(T, self.net.cond_shape(n), "T")
         _check_dev(y0, (n, ns), "y0")
         _check_dev(lam, (n, ns), "lam")
         if log_alpha is not None:
@@ -445,6 +460,29 @@ class Workspace:
         return out
 
 
+def _replay(ws, y0, T, tape, tape_len, rtol=1e-6, atol=1e-20, log_alpha=None, stream=None):
+    import torch
+    n, ns = T.shape[0], ws.net.n_species
+    _check_dev(T, ws.net.cond_shape(n), "T")
+    _check_dev(y0, (n, ns), "y0")
+    if log_alpha is not None:
+        _check_dev(log_alpha, (ws.net.n_reactions,), "log_alpha")
+    if tape.dim() != 3 or tape.shape[0] != n or tape.shape[2] != 2 or not tape.is_contiguous():
+        raise ValueError("tape must be the [n, tape_cap, 2] tensor returned by integrate")
+    yf = torch.empty_like(y0)
+    status = torch.empty(n, dtype=torch.int32, device=y0.device)
+    o = IntegOpts(float(rtol), float(atol), 0.0, 5, 1, 1)
+    check(lib.ac_replay(ws.handle, _ptr(log_alpha), n, _ptr(y0), _ptr(T), C.byref(o), _ptr(tape),
+                        int(tape.shape[1]), _ptr(tape_len), _ptr(yf), _ptr(status), None,
+                        _stream(stream)), "ac_replay")
+    return {"y_final": yf, "status": status}
+
+
+Workspace.replay = _replay
+Workspace.replay.__doc__ = """ac_replay: y(t_end) replayed along a recorded tape with converged
+correctors. Returns dict of device tensors y_final [n, ns], status [n]."""
+
+
 def tape_to_numpy(tape_tensor):
     """Device tape tensor -> numpy structured array of EVENT_DTYPE."""
     raw = tape_tensor.cpu().numpy()
@@ -467,11 +505,29 @@ class Integrate:
     integrator (recording the step sequence) and returns y(t_end); its
     backward replays that sequence through ac_integrate_adjoint and returns
     dL/dlog_alpha (summed over cells) and dL/dy0. opts: dict with rtol,
-    atol, q_max, max_steps, tape_cap (events kept per cell)."""
+    atol, q_max, max_steps and tape_cap (events kept per cell; by default
+    the tape starts at 4,096 events and the forward run is repeated with a
+    four times longer tape while any cell overflows it, up to what
+    max_steps can produce). A cell that does not reach t_end (status other
+    than AC_CELL_OK) raises IncompleteIntegration in the forward pass, and a
+    cell whose adjoint is not complete raises it in the backward pass,
+    rather than returning values that are not y(t_end) or its gradient."""
 
     @staticmethod
     def apply(log_alpha, y0, T, ws, t_end, opts=None):
         return _integrate_fn().apply(log_alpha, y0, T, ws, t_end, opts or {})
+
+
+class IncompleteIntegration(RuntimeError):
+    """Some cells stopped before t_end (status per cell in .status)."""
+
+    def __init__(self, where: str, status):
+        import numpy as _np
+        st = _np.asarray(status)
+        bad = _np.flatnonzero(st != AC_CELL_OK)
+        super().__init__(f"{where}: {bad.size} of {st.size} cells did not complete "
+                         f"(first cells {bad[:8].tolist()}, statuses {st[bad[:8]].tolist()})")
+        self.status = st
 
 
 _FN = None
@@ -488,14 +544,29 @@ def _integrate_fn():
         def forward(ctx, log_alpha, y0, T, ws, t_end, opts):
             rtol = opts.get("rtol", 1e-6)
             atol = opts.get("atol", 1e-20)
-            cap = opts.get("tape_cap", 2 * opts.get("max_steps", 100000) + 16)
-            y = y0.detach().clone().contiguous()
+            max_steps = opts.get("max_steps", 100000)
+            # each accepted step records one event, and each rejection or
+            # order change at most one more
+            cap_max = 2 * max_steps + 16
+            cap = opts.get("tape_cap", min(4096, cap_max))
             la = log_alpha.detach().contiguous()
-            res = ws.integrate(y, T, t_end, rtol=rtol, atol=atol, q_max=opts.get("q_max", 5),
-                               max_steps=opts.get("max_steps", 100000), log_alpha=la,
-                               tape_cap=cap)
+            while True:
+                y = y0.detach().clone().contiguous()
+                res = ws.integrate(y, T, t_end, rtol=rtol, atol=atol, q_max=opts.get("q_max", 5),
+                                   max_steps=max_steps, log_alpha=la, tape_cap=cap)
+                overflow = bool((res["tape_len"] < 0).any())
+                if not overflow or "tape_cap" in opts or cap >= cap_max:
+                    break
+                cap = min(4 * cap, cap_max)
+            status = res["status"].cpu().numpy()
+            if (status != AC_CELL_OK).any():
+                raise IncompleteIntegration("Integrate forward", status)
+            if overflow:
+                raise IncompleteIntegration("Integrate forward (tape overflow)",
+                                            np.where(res["tape_len"].cpu().numpy() < 0,
+                                                     AC_CELL_TAPE, AC_CELL_OK))
             ctx.ws, ctx.rtol, ctx.atol = ws, rtol, atol
-            ctx.tape, ctx.tape_len, ctx.status = res["tape"], res["tape_len"], res["status"]
+            ctx.tape, ctx.tape_len = res["tape"], res["tape_len"]
             ctx.save_for_backward(la, y0.detach().contiguous(), T)
             return y
 
@@ -504,6 +575,9 @@ def _integrate_fn():
             la, y0, T = ctx.saved_tensors
             r = ctx.ws.adjoint(y0, T, ctx.tape, ctx.tape_len, gy.contiguous(), rtol=ctx.rtol,
                                atol=ctx.atol, log_alpha=la, want_glog=True)
+            status = r["status"].cpu().numpy()
+            if (status != AC_CELL_OK).any():
+                raise IncompleteIntegration("Integrate backward", status)
             return r["dL_dlogalpha"], r["dL_dy0"], None, None, None, None
 
     _FN = _Integrate

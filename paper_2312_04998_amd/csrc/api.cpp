@@ -157,7 +157,8 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
   std::string err;
   try {
     err = ac::build_network(desc->n_species, desc->n_reactions, desc->reactants, desc->products,
-                            desc->alpha, desc->beta, desc->gamma, desc->composition, desc->n_elem,
+                            desc->alpha, desc->beta, desc->gamma, desc->rate_law,
+                            desc->composition, desc->n_elem,
                             desc->check_balance != 0, desc->layout, desc->ordering, desc->chunk,
                             desc->sell_c, desc->sell_sigma, net->host, &code);
   } catch (const std::bad_alloc &) {
@@ -209,6 +210,7 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
   d.nnz_j = int(H.j_col.size());
   d.layout = H.layout;
   d.block = desc->block ? desc->block : 512;
+  d.n_cond = H.law.empty() ? 1 : AC_NCOND;
   d.log_alpha = at<double>(b, o_la);
   d.beta = at<double>(b, o_be);
   d.gamma = at<double>(b, o_ga);
@@ -626,6 +628,26 @@ static ac_status adj_reserve(ac_ws *ws, int tape_cap, bool all_states, hipStream
   A.segcap = segcap;
   A.all_states = all_states ? 1 : 0;
   return AC_OK;
+}
+
+ac_status ac_replay(ac_ws *ws, const double *log_alpha, int64_t n_cells, const double *y0,
+                    const double *T, const ac_integ_opts *opts, const ac_event *tape,
+                    int32_t tape_cap, const int32_t *tape_len, double *y_final,
+                    int32_t *cell_status, int32_t *cell_stats, ac_stream stream) {
+  if (ac_status s = integ_args(ws, n_cells, y0, T, 0.0, opts)) return s;
+  if (tape_cap <= 0) return fail(AC_EINVAL, "tape_cap must be > 0");
+  if (n_cells && (!tape || !tape_len || !y_final))
+    return fail(AC_EINVAL, "null tape, tape_len or y_final");
+  if (!n_cells) return AC_OK;
+  hipStream_t st = hipStream_t(stream);
+  // the replay keeps its checkpoints; no converged states are stored
+  if (ac_status s = adj_reserve(ws, tape_cap, false, st)) return s;
+  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, 0.0, opts->q_max, opts->max_steps};
+  ac::AdjIO io{reinterpret_cast<const ac::AcEvent *>(tape), tape_len, tape_cap, y0, T, nullptr,
+               y_final, nullptr, nullptr, cell_status, cell_stats};
+  hipError_t e = ac::launch_adjoint(ws->net->d, log_alpha, n_cells, io, P, ws->W, ws->A,
+                                    ws->queue, ws->n_slots, st);
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_replay launch");
 }
 
 ac_status ac_integrate_adjoint(ac_ws *ws, const double *log_alpha, int64_t n_cells,

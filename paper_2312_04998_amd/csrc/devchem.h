@@ -319,10 +319,12 @@ __device__ __forceinline__ void load_cell(const double *__restrict__ src, double
   for (int i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
 }
 
-// Reaction record: ln alpha, beta, gamma, reactant pair (two 16-byte loads).
+// Reaction record: ln alpha, beta', gamma', reactant pair and rate law (two
+// 16-byte loads); beta' and gamma' are the law's parameters in the form of
+// rate_k.
 struct Rx {
   double la, beta, gamma;
-  uint32_t pair;
+  uint32_t pair, law;
 };
 
 __device__ __forceinline__ Rx load_rx(const DNet &n, int j) {
@@ -332,13 +334,59 @@ __device__ __forceinline__ Rx load_rx(const DNet &n, int j) {
   r.beta = __hiloint2double(int(a.w), int(a.z));
   r.gamma = __hiloint2double(int(b.y), int(b.x));
   r.pair = b.z;
+  r.law = b.w;
   return r;
 }
 
-// k_j = exp(ln alpha_j + beta_j ln(T/300) - gamma_j / T)
-__device__ __forceinline__ double kooij(double la, double beta, double gamma, double L,
-                                        double invT) {
-  return exp(la + beta * L - gamma * invT);
+// A cell's conditions in the form the rate laws use: L = ln(T/300),
+// invT = 1/T and, when the network has rate laws, A_V, ln(zeta/zeta_0) and
+// ln G_0.
+struct Env {
+  double L, invT, av, lnz, lng;
+};
+
+__device__ __forceinline__ Env env_of(const double *p, int nc) {
+  Env e;
+  const double Tc = p[0];
+  e.L = log(Tc / 300.0);
+  e.invT = 1.0 / Tc;
+  if (nc > 1) {
+    e.av = p[1];
+    e.lnz = log(p[2]);
+    e.lng = log(p[3]);
+  } else {
+    e.av = e.lnz = e.lng = 0.0;
+  }
+  return e;
+}
+
+__device__ __forceinline__ Env cell_env(const double *__restrict__ cond, int64_t c, int nc) {
+  return env_of(cond + c * nc, nc);
+}
+
+// Conditions a cell's integration accepts: T > 0 and the others >= 0, all
+// finite.
+__device__ __forceinline__ bool cell_env_ok(const double *__restrict__ cond, int64_t c, int nc) {
+  const double *p = cond + c * nc;
+  bool ok = isfinite(p[0]) && p[0] > 0.0;
+  for (int i = 1; i < nc; ++i) ok = ok && isfinite(p[i]) && p[i] >= 0.0;
+  return ok;
+}
+
+// k_j = exp(ln alpha + beta' ln(T/300) - gamma' X + Y), with (X, Y) =
+// (1/T, 0) for the modified Arrhenius law, (-, ln zeta) for direct
+// cosmic-ray ionisation (beta' = gamma' = 0), (1, ln zeta) for cosmic-ray
+// induced photons (gamma' = -ln(gamma / (1 - albedo))) and (A_V, ln G_0)
+// for FUV photoreactions (beta' = 0).
+__device__ __forceinline__ double rate_k(double la, double beta, double gamma, uint32_t law,
+                                         const Env &e) {
+  const double X = law == AC_LAW_PHOTO ? e.av : law == AC_LAW_CRPHOT ? 1.0 : e.invT;
+  const double Y = law == AC_LAW_KOOIJ ? 0.0 : law == AC_LAW_PHOTO ? e.lng : e.lnz;
+  return exp(la + beta * e.L - gamma * X + Y);
+}
+
+__device__ __forceinline__ double rate_k(const Rx &r, const Env &e) {
+  return rate_k(r.la, r.beta, r.gamma, r.law, e);
 }
 
 __device__ __forceinline__ double reaction_rate(uint32_t pair, double k, const double *ys) {
@@ -353,7 +401,7 @@ __device__ __forceinline__ double reaction_rate(uint32_t pair, double k, const d
 constexpr int RXU = 4;
 template <int NT, typename F>
 __device__ __forceinline__ void for_reactions(const DNet &n, const double *__restrict__ la_over,
-                                              double L, double invT, F fn) {
+                                              const Env &env, F fn) {
   for (int j0 = threadIdx.x; j0 < n.nr; j0 += RXU * NT) {
     Rx r[RXU];
 #pragma unroll
@@ -367,14 +415,9 @@ __device__ __forceinline__ void for_reactions(const DNet &n, const double *__res
 #pragma unroll
     for (int u = 0; u < RXU; ++u) {
       const int j = j0 + u * NT;
-      if (j < n.nr) fn(j, kooij(r[u].la, r[u].beta, r[u].gamma, L, invT), r[u].pair);
+      if (j < n.nr) fn(j, rate_k(r[u], env), r[u].pair);
     }
   }
-}
-
-__device__ __forceinline__ void cell_temperature(double Tc, double &L, double &invT) {
-  L = log(Tc / 300.0);
-  invT = 1.0 / Tc;
 }
 
 }  // namespace ac

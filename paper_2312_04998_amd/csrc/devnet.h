@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "../../include/astrochem.h"
+
 namespace ac {
 
 constexpr int LAYOUT_CSR = 0, LAYOUT_SELL = 1, LAYOUT_COO = 2, LAYOUT_RUNS = 3, LAYOUT_CCS = 4;
@@ -26,6 +28,7 @@ struct DSched {
 
 struct DNet {
   int ns, nr, nnz_j, layout, block;
+  int n_cond;                  // doubles of per-cell conditions: 1 (T) or AC_NCOND
   const double *log_alpha, *beta, *gamma;
   const uint32_t *rpair;       // reactant a | b << 16 (0xFFFF none)
   const uint4 *rxpack;         // planes of nr words: (la, beta) | (gamma, rpair) | S column

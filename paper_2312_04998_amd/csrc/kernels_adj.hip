@@ -223,7 +223,6 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
 
     for (int i = 0; i < ST_N; ++i) cx.cnt[i] = 0;
     const double *y0 = io.y0 + cell * ns;
-    const double Tc = io.T[cell];
     const AcEvent *ev = io.ev + cell * io.cap;
     const int nev = io.len[cell];
     double *grow = io.g_cells ? io.g_cells + cell * nr : nullptr;
@@ -232,7 +231,7 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
       const double y = y0[i];
       if (!(isfinite(y) && y >= 0.0)) bad = true;
     }
-    bad = wg_any<NT>(bad, red) || !(isfinite(Tc) && Tc > 0.0);
+    bad = wg_any<NT>(bad, red) || !cell_env_ok(io.T, cell, n.n_cond);
     // a tape that overflowed, or holds an order outside 1..QMAX, is not replayed
     bool badtape = nev < 0 || nev > io.cap;
     if (!badtape) {
@@ -246,14 +245,13 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
     if (grow)
       for (int j = threadIdx.x; j < nr; j += NT) grow[j] = 0.0;
     for (int x = threadIdx.x; x < ns; x += NT) {
-      Db[x] = io.lam[cell * ns + x];
+      Db[x] = io.lam ? io.lam[cell * ns + x] : 0.0;
       for (int m = 1; m < NDROW; ++m) Db[size_t(m) * ns + x] = 0.0;
     }
     __syncthreads();
     if (status == AC_CELL_OK && nev > 0) {
-      double L, invT;
-      cell_temperature(Tc, L, invT);
-      for_reactions<NT>(n, la_over, L, invT, [&](int j, double kj, uint32_t) { cx.kg[j] = kj; });
+      const Env env = cell_env(io.T, cell, n.n_cond);
+      for_reactions<NT>(n, la_over, env, [&](int j, double kj, uint32_t) { cx.kg[j] = kj; });
       for (int x = threadIdx.x; x < ns; x += NT) {
         cx.D[x] = y0[x];
         for (int m = 1; m < NDROW; ++m) cx.D[size_t(m) * ns + x] = 0.0;
@@ -273,7 +271,7 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
             cM = 0.0;
           }
           replay_step<NT>(cx, v, E.q, E.val, P.rtol, P.atol, ns, cM);
-          if (A.all_states)   // nstep < nev <= cap = segcap
+          if (A.all_states && io.gy0)   // nstep < nev <= cap = segcap
             for (int x = threadIdx.x; x < ns; x += NT) segY[size_t(nstep) * ns + x] = yn[x];
           ++nstep;
         } else if (E.type == EV_RESCALE) {
@@ -289,9 +287,10 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
       if (io.y_final)
         for (int x = threadIdx.x; x < ns; x += NT) io.y_final[cell * ns + x] = cx.D[x];
       __syncthreads();
-      // reverse sweep, one checkpointed segment at a time
-      int e_end = nev;
-      for (int s = nck - 1; s >= 0; --s) {
+      // reverse sweep, one checkpointed segment at a time (skipped when only
+      // the replayed state is asked for)
+      int e_end = io.gy0 ? nev : 0;
+      for (int s = io.gy0 ? nck - 1 : -1; s >= 0; --s) {
         const int e0 = ckev[s];
         int i = 0;
         const double *sy = segY;
@@ -331,7 +330,7 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
         e_end = e0;
       }
       // events before the first accepted step: resamplings and the start
-      for (int e = e_end - 1; e >= 0; --e) {
+      for (int e = e_end - 1; io.gy0 && e >= 0; --e) {
         const AcEvent E = ev[e];
         if (E.type == EV_RESCALE) {
           apply_resample<NT, true>(resample_matrix<NT>(cx, E.q, E.val), Db, E.q, ns);
@@ -353,7 +352,8 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
     } else if (io.y_final) {
       for (int x = threadIdx.x; x < ns; x += NT) io.y_final[cell * ns + x] = y0[x];
     }
-    for (int x = threadIdx.x; x < ns; x += NT) io.gy0[cell * ns + x] = Db[x];
+    if (io.gy0)
+      for (int x = threadIdx.x; x < ns; x += NT) io.gy0[cell * ns + x] = Db[x];
     if (threadIdx.x == 0 && io.status) io.status[cell] = status;
     if (threadIdx.x == 0 && io.stats) {
       int *st = io.stats + cell * ST_N;

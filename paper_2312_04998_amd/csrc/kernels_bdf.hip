@@ -89,20 +89,18 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
     for (int i = 0; i < ST_N; ++i) cx.cnt[i] = 0;
     int tlen = 0;
     double *ycell = y + cell * ns;
-    const double Tc = T[cell];
     bool bad = false;
     for (int i = threadIdx.x; i < ns; i += NT) {
       const double v = ycell[i];
       if (!(isfinite(v) && v >= 0.0)) bad = true;
     }
-    bad = wg_any<NT>(bad, red) || !(isfinite(Tc) && Tc > 0.0);
+    bad = wg_any<NT>(bad, red) || !cell_env_ok(T, cell, n.n_cond);
     int status = AC_CELL_OK, q = 1, steps = 0;
     const bool run = !bad && t_end > 0.0;
     if (bad) status = AC_CELL_BADINPUT;
     if (run) {
-      double L, invT;
-      cell_temperature(Tc, L, invT);
-      for_reactions<NT>(n, la_over, L, invT, [&](int j, double kj, uint32_t) { cx.kg[j] = kj; });
+      const Env env = cell_env(T, cell, n.n_cond);
+      for_reactions<NT>(n, la_over, env, [&](int j, double kj, uint32_t) { cx.kg[j] = kj; });
       for (int x = threadIdx.x; x < ns; x += NT) {
         const double v = ycell[x];
         yn[x] = v;

@@ -22,10 +22,9 @@ __global__ __launch_bounds__(NT) void k_rates(DNet n, const double *__restrict__
                                               int64_t n_cells, const double *__restrict__ T,
                                               double *__restrict__ k) {
   for (int64_t c = blockIdx.x; c < n_cells; c += gridDim.x) {
-    double L, invT;
-    cell_temperature(T[c], L, invT);
+    const Env env = cell_env(T, c, n.n_cond);
     double *kc = k + c * n.nr;
-    for_reactions<NT>(n, la_over, L, invT,
+    for_reactions<NT>(n, la_over, env,
                       [&](int j, double kj, uint32_t) { __builtin_nontemporal_store(kj, kc + j); });
   }
 }
@@ -47,8 +46,8 @@ __global__ __launch_bounds__(NT) void k_rhs(DNet n, const double *__restrict__ l
     load_cell<NT>(y + c * ns, ys, ns);
     if (LAYOUT == LAYOUT_CCS)
       for (int i = threadIdx.x; i < ns; i += NT) part[i] = 0.0;
-    double L = 0.0, invT = 0.0;
-    if (!PREK) cell_temperature(T[c], L, invT);
+    Env env{};
+    if (!PREK) env = cell_env(T, c, n.n_cond);
     __syncthreads();
     if (PREK) {
       // every coefficient and reactant pair of a lane requested before use
@@ -68,7 +67,7 @@ __global__ __launch_bounds__(NT) void k_rhs(DNet n, const double *__restrict__ l
           if (j0 + u * NT < nr) rs[j0 + u * NT] = reaction_rate(pr[u], kv[u], ys);
       }
     } else {
-      for_reactions<NT>(n, la_over, L, invT,
+      for_reactions<NT>(n, la_over, env,
                         [&](int j, double kj, uint32_t pair) { rs[j] = reaction_rate(pair, kj, ys); });
     }
     __syncthreads();
@@ -115,9 +114,7 @@ __global__ __launch_bounds__(NT) void k_rhs2(DNet n, const double *__restrict__ 
     const bool two = c + 1 < n_cells;
     for (int i = threadIdx.x; i < ns; i += NT)
       yy[i] = make_double2(y[c * ns + i], two ? y[(c + 1) * ns + i] : 0.0);
-    double L0, invT0, L1, invT1;
-    cell_temperature(T[c], L0, invT0);
-    cell_temperature(two ? T[c + 1] : T[c], L1, invT1);
+    const Env e0 = cell_env(T, c, n.n_cond), e1 = cell_env(T, two ? c + 1 : c, n.n_cond);
     __syncthreads();
     for (int j0 = threadIdx.x; j0 < nr; j0 += RXU * NT) {
       Rx r[RXU];
@@ -134,8 +131,8 @@ __global__ __launch_bounds__(NT) void k_rhs2(DNet n, const double *__restrict__ 
         const int j = j0 + u * NT;
         if (j < nr) {
           const double2 ya = yy[r[u].pair & 0xFFFFu];
-          double r0 = kooij(r[u].la, r[u].beta, r[u].gamma, L0, invT0) * ya.x;
-          double r1 = kooij(r[u].la, r[u].beta, r[u].gamma, L1, invT1) * ya.y;
+          double r0 = rate_k(r[u], e0) * ya.x;
+          double r1 = rate_k(r[u], e1) * ya.y;
           const uint32_t b = r[u].pair >> 16;
           if (b != 0xFFFFu) {
             const double2 yb = yy[b];
@@ -174,9 +171,8 @@ __global__ __launch_bounds__(NT) void k_jac(DNet n, const double *__restrict__ l
   double *part = ks + nr;
   for (int64_t c = blockIdx.x; c < n_cells; c += gridDim.x) {
     load_cell<NT>(y + c * ns, ys, ns);
-    double L, invT;
-    cell_temperature(T[c], L, invT);
-    for_reactions<NT>(n, la_over, L, invT, [&](int j, double kj, uint32_t) { ks[j] = kj; });
+    const Env env = cell_env(T, c, n.n_cond);
+    for_reactions<NT>(n, la_over, env, [&](int j, double kj, uint32_t) { ks[j] = kj; });
     __syncthreads();
     runsum_partials<NT>(n.jtail, ks, ys, part);
     __syncthreads();
@@ -231,9 +227,7 @@ __device__ __forceinline__ void jac2_pass(const DNet &n, const double *__restric
   const int ns = n.ns, nr = n.nr, nnz = n.nnz_j;
   for (int i = threadIdx.x; i < ns; i += NT)
     yy[i] = make_double2(y[c * ns + i], two ? y[(c + 1) * ns + i] : 0.0);
-  double L0, invT0, L1, invT1;
-  cell_temperature(T[c], L0, invT0);
-  cell_temperature(two ? T[c + 1] : T[c], L1, invT1);
+  const Env e0 = cell_env(T, c, n.n_cond), e1 = cell_env(T, two ? c + 1 : c, n.n_cond);
   for (int j0 = threadIdx.x; j0 < nr; j0 += RXU * NT) {
     Rx r[RXU];
 #pragma unroll
@@ -248,8 +242,8 @@ __device__ __forceinline__ void jac2_pass(const DNet &n, const double *__restric
     for (int u = 0; u < RXU; ++u) {
       const int j = j0 + u * NT;
       if (j < nr)
-        kk[j] = make_double2(kooij(r[u].la, r[u].beta, r[u].gamma, L0, invT0),
-                             kooij(r[u].la, r[u].beta, r[u].gamma, L1, invT1));
+        kk[j] = make_double2(rate_k(r[u], e0),
+                             rate_k(r[u], e1));
     }
   }
   __syncthreads();
@@ -359,6 +353,7 @@ __global__ __launch_bounds__(NT) void k_rhs_jac2(DNet n, const double *__restric
   }
 }
 
+
 // -------------------------------------------------------------------- VJP
 //
 // w_j = (S^T v)_j from the packed net column of S; gy_a = sum over reactant
@@ -387,10 +382,9 @@ __global__ __launch_bounds__(NT) void k_vjp(DNet n, const double *__restrict__ l
   for (int64_t c = blockIdx.x; c < n_cells; c += gridDim.x) {
     load_cell<NT>(y + c * ns, ys, ns);
     load_cell<NT>(v + c * ns, vs, ns);
-    double L, invT;
-    cell_temperature(T[c], L, invT);
+    const Env env = cell_env(T, c, n.n_cond);
     __syncthreads();
-    for_reactions<NT>(n, la_over, L, invT, [&](int j, double kj, uint32_t pair) {
+    for_reactions<NT>(n, la_over, env, [&](int j, double kj, uint32_t pair) {
       const uint4 col = n.rxpack[2 * n.nr + j];
       const uint32_t w4[4] = {col.x, col.y, col.z, col.w};
       double w = 0.0;
@@ -444,9 +438,7 @@ __global__ __launch_bounds__(NT) void k_vjp2(DNet n, const double *__restrict__ 
       yy[i] = make_double2(y[c * ns + i], two ? y[(c + 1) * ns + i] : 0.0);
       vv[i] = make_double2(v[c * ns + i], two ? v[(c + 1) * ns + i] : 0.0);
     }
-    double L0, invT0, L1, invT1;
-    cell_temperature(T[c], L0, invT0);
-    cell_temperature(two ? T[c + 1] : T[c], L1, invT1);
+    const Env e0 = cell_env(T, c, n.n_cond), e1 = cell_env(T, two ? c + 1 : c, n.n_cond);
     __syncthreads();
     for (int j0 = threadIdx.x; j0 < nr; j0 += RXU * NT) {
       Rx r[RXU];
@@ -476,8 +468,8 @@ __global__ __launch_bounds__(NT) void k_vjp2(DNet n, const double *__restrict__ 
             w1 += coef * vq.y;
           }
         }
-        const double k0 = kooij(r[u].la, r[u].beta, r[u].gamma, L0, invT0);
-        const double k1 = kooij(r[u].la, r[u].beta, r[u].gamma, L1, invT1);
+        const double k0 = rate_k(r[u], e0);
+        const double k1 = rate_k(r[u], e1);
         kw[j] = make_double2(k0 * w0, k1 * w1);
         if (prow) {
           const uint32_t pair = r[u].pair;

@@ -223,9 +223,9 @@ void build_schedule(const std::vector<std::vector<uint32_t>> &seg_items,
 
 std::string build_network(int ns, int nr, const int32_t *reactants, const int32_t *products,
                           const double *alpha, const double *beta, const double *gamma,
-                          const int8_t *composition, int n_elem, bool check_balance, int layout,
-                          int ordering, int chunk, int sell_c, int sell_sigma, HostNet &H,
-                          int *code) {
+                          const int8_t *law, const int8_t *composition, int n_elem,
+                          bool check_balance, int layout, int ordering, int chunk, int sell_c,
+                          int sell_sigma, HostNet &H, int *code) {
   *code = AC_EINVAL;
   if (ns <= 0 || nr <= 0) return "n_species and n_reactions must be positive";
   if (ns > AC_MAX_SPECIES || nr > AC_MAX_REACTIONS) {
@@ -250,6 +250,7 @@ std::string build_network(int ns, int nr, const int32_t *reactants, const int32_
   H.log_alpha.resize(nr);
   H.beta.assign(beta, beta + nr);
   H.gamma.assign(gamma, gamma + nr);
+  if (law) H.law.assign(law, law + nr);
   H.rpair.resize(nr);
   // net stoichiometry per reaction (sorted by species)
   std::vector<std::map<int, int>> col(nr);
@@ -258,6 +259,10 @@ std::string build_network(int ns, int nr, const int32_t *reactants, const int32_
         !std::isfinite(gamma[j]))
       return "reaction " + std::to_string(j) + ": alpha must be positive and finite, beta/gamma finite";
     H.log_alpha[j] = std::log(alpha[j]);
+    if (law && (law[j] < AC_LAW_KOOIJ || law[j] > AC_LAW_PHOTO))
+      return "reaction " + std::to_string(j) + ": unknown rate law";
+    if (law && law[j] == AC_LAW_CRPHOT && !(gamma[j] > 0.0))
+      return "reaction " + std::to_string(j) + ": cosmic-ray photon efficiency gamma must be > 0";
     int nreac = 0, slot[2] = {-1, -1};
     for (int s = 0; s < AC_MAX_REACTANTS; ++s) {
       int a = reactants[j * AC_MAX_REACTANTS + s];
@@ -397,10 +402,23 @@ std::string build_network(int ns, int nr, const int32_t *reactants, const int32_
     uint32_t *p0 = &H.rxpack[size_t(j) * 4];
     uint32_t *p1 = &H.rxpack[(size_t(nr) + j) * 4];
     uint32_t *p2 = &H.rxpack[(size_t(2) * nr + j) * 4];
-    const double la_b[2] = {H.log_alpha[j], H.beta[j]};
+    // every law as ln k = ln alpha + beta' ln(T/300) - gamma' X + Y, with X
+    // and Y per-cell terms chosen by the law (devchem.h rate_k)
+    const int lw = H.law.empty() ? AC_LAW_KOOIJ : H.law[j];
+    double b2 = H.beta[j], g2 = H.gamma[j];
+    if (lw == AC_LAW_CRP) {
+      b2 = 0.0;
+      g2 = 0.0;
+    } else if (lw == AC_LAW_CRPHOT) {
+      g2 = -std::log(H.gamma[j] / (1.0 - AC_GRAIN_ALBEDO));   // X = 1
+    } else if (lw == AC_LAW_PHOTO) {
+      b2 = 0.0;
+    }
+    const double la_b[2] = {H.log_alpha[j], b2};
     std::memcpy(p0, la_b, sizeof(la_b));
-    std::memcpy(p1, &H.gamma[j], sizeof(double));
+    std::memcpy(p1, &g2, sizeof(double));
     p1[2] = H.rpair[j];
+    p1[3] = uint32_t(lw);
     uint16_t half[8];
     for (int q = 0; q < 8; ++q) half[q] = 0xFFFF;
     int q = 0;

@@ -64,9 +64,14 @@ struct HostNet {
   int ns = 0, nr = 0;
   // reaction data
   std::vector<double> log_alpha, beta, gamma;
+  // rate law per reaction (AC_LAW_*), empty when every reaction follows the
+  // modified Arrhenius law; the device records carry the law code and the
+  // parameters in the form ln k = ln alpha + beta' ln(T/300) - gamma' X + Y
+  // (see devchem.h rate_k)
+  std::vector<int8_t> law;
   std::vector<uint32_t> rpair;        // reactant a | b << 16, 0xFFFF = none
-  // per reaction, in three planes of nr 16-byte words: (ln alpha, beta),
-  // (gamma, rpair, 0), and the net column of S as up to 8 16-bit
+  // per reaction, in three planes of nr 16-byte words: (ln alpha, beta'),
+  // (gamma', rpair, law), and the net column of S as up to 8 16-bit
   // (species | coef << 11) halves (0xFFFF = none)
   std::vector<uint32_t> rxpack;
   // S in CSR (natural rows, reactions ascending) and CCS (per reaction)
@@ -91,9 +96,9 @@ struct HostNet {
 // Returns an empty string on success, else the reason (code in *code).
 std::string build_network(int ns, int nr, const int32_t *reactants, const int32_t *products,
                           const double *alpha, const double *beta, const double *gamma,
-                          const int8_t *composition, int n_elem, bool check_balance, int layout,
-                          int ordering, int chunk, int sell_c, int sell_sigma, HostNet &out,
-                          int *code);
+                          const int8_t *law, const int8_t *composition, int n_elem,
+                          bool check_balance, int layout, int ordering, int chunk, int sell_c,
+                          int sell_sigma, HostNet &out, int *code);
 
 // Species order by the chosen rule over the pattern of S (CSR rows).
 std::vector<int32_t> species_order(int ns, const std::vector<int32_t> &row_ptr,

@@ -62,6 +62,7 @@ class Network:
     composition: np.ndarray
     names: List[str]
     rtype: np.ndarray
+    law: Optional[np.ndarray] = None   # int8 [n_reactions] rate-law code, None = all Kooij
 
     @property
     def n_species(self) -> int:
@@ -77,7 +78,8 @@ class Network:
         return Network(self.reactants[idx].copy(), self.products[idx].copy(),
                        self.alpha[idx].copy(), self.beta[idx].copy(),
                        self.gamma[idx].copy(), self.composition.copy(),
-                       list(self.names), self.rtype[idx].copy())
+                       list(self.names), self.rtype[idx].copy(),
+                       None if self.law is None else self.law[idx].copy())
 
 
 def network_from_lists(n_species: int,
@@ -426,6 +428,60 @@ def make_cells(net: Network, n_cells: int, seed: int,
         ne = y0 @ qq                     # net positive charge of the heavy species
         y0[:, e] = np.where(ne > 0, ne, y0[:, e])
     return Cells(Tv, nh, np.ascontiguousarray(y0))
+
+
+# --------------------------------------------------------------------------
+# rate laws by reaction type and the per-cell conditions they read
+# --------------------------------------------------------------------------
+
+# Rate-law codes: modified Arrhenius (Kooij), direct cosmic-ray ionisation,
+# cosmic-ray induced photoreaction, interstellar FUV photoreaction. The
+# coefficients depend on the temperature, the cosmic-ray ionisation rate and
+# the FUV intensity (Sec. 3); per-cell conditions are (T, A_V, zeta/zeta_0,
+# G_0).
+LAW_KOOIJ, LAW_CRP, LAW_CRPHOT, LAW_PHOTO = 0, 1, 2, 3
+N_COND = 4
+
+
+def with_rate_laws(net: Network, seed: int) -> Network:
+    """A copy of ``net`` whose one-body reactions follow the cosmic-ray and
+    photo laws: 30 % direct cosmic-ray ionisation (alpha log-uniform on
+    [1e-18, 1e-16] s^-1 at zeta_0), 30 % cosmic-ray induced photoreactions
+    (alpha log-uniform on [5e-18, 3e-17], beta uniform on (-0.5, 0.5),
+    efficiency gamma log-uniform on [10, 5000]), 40 % FUV photoreactions
+    (alpha log-uniform on [1e-11, 1e-9] s^-1 at G_0 = 1, attenuation gamma
+    uniform on (0.5, 3.5) per magnitude). Two-body and recombination
+    reactions keep the Kooij law and their parameters."""
+    rng = np.random.default_rng(seed)
+    law = np.zeros(net.n_reactions, np.int8)
+    alpha, beta, gamma = net.alpha.copy(), net.beta.copy(), net.gamma.copy()
+    one = np.flatnonzero(net.rtype == 1)
+    u = rng.uniform(size=one.size)
+    crp, crph, ph = one[u < 0.3], one[(u >= 0.3) & (u < 0.6)], one[u >= 0.6]
+    law[crp], law[crph], law[ph] = LAW_CRP, LAW_CRPHOT, LAW_PHOTO
+    alpha[crp] = np.exp(rng.uniform(np.log(1e-18), np.log(1e-16), crp.size))
+    beta[crp], gamma[crp] = 0.0, 0.0
+    alpha[crph] = np.exp(rng.uniform(np.log(5e-18), np.log(3e-17), crph.size))
+    beta[crph] = rng.uniform(-0.5, 0.5, crph.size)
+    gamma[crph] = np.exp(rng.uniform(np.log(10.0), np.log(5000.0), crph.size))
+    alpha[ph] = np.exp(rng.uniform(np.log(1e-11), np.log(1e-9), ph.size))
+    beta[ph] = 0.0
+    gamma[ph] = rng.uniform(0.5, 3.5, ph.size)
+    return dataclasses.replace(net, alpha=alpha, beta=beta, gamma=gamma, law=law)
+
+
+def make_conditions(T: np.ndarray, seed: int, Av_range=(0.1, 20.0), zeta_range=(0.1, 10.0),
+                    G0_range=(0.1, 100.0)) -> np.ndarray:
+    """Per-cell conditions [n_cells, 4] = (T, A_V, zeta/zeta_0, G_0) around
+    given temperatures, the other three log-uniform on their ranges."""
+    rng = np.random.default_rng(seed + 104729)
+    n = len(T)
+    out = np.empty((n, N_COND))
+    out[:, 0] = T
+    out[:, 1] = np.exp(rng.uniform(np.log(Av_range[0]), np.log(Av_range[1]), n))
+    out[:, 2] = np.exp(rng.uniform(np.log(zeta_range[0]), np.log(zeta_range[1]), n))
+    out[:, 3] = np.exp(rng.uniform(np.log(G0_range[0]), np.log(G0_range[1]), n))
+    return out
 
 
 # --------------------------------------------------------------------------

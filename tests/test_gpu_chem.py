@@ -270,3 +270,39 @@ def test_rhs_jac_fused_equals_separate(acm, torch_dev, medium_net, med_cells, n_
         acm.ac_jac(N, None, y, T, j1)
         acm.ac_rhs_jac(N, None, y, T, d2, j2)
         assert torch.equal(d1, d2) and torch.equal(j1, j2), layout
+
+
+def test_rhs_jac_fused_full_batch(acm, torch_dev, oracle_mod, medium_net):
+    """The benchmarked call at the benchmarked size and configuration: one
+    ac_rhs_jac over all 65,536 cells of the 470/4600 workload with the SELL
+    layout in natural order, so every workgroup makes many passes and carries
+    its LDS sentinels (the (1, 1) density pair and the (0, 0) slot pair)
+    from pass to pass. Bit-identical to ac_rhs followed by ac_jac; 48
+    sampled cells against the oracle."""
+    torch = torch_dev
+    net = medium_net
+    C = 65536
+    cells = synthnet.make_cells(net, C, synthnet.SEED_BASE + 1)
+    N = acm.Network.from_synth(net, layout="sell", ordering="natural")
+    y, T = _t(torch, cells.y0), _t(torch, cells.T)
+    d2 = torch.empty_like(y)
+    j2 = torch.empty((C, N.nnz_j), dtype=torch.float64, device="cuda")
+    acm.ac_rhs_jac(N, None, y, T, d2, j2)
+    d1 = torch.empty_like(y)
+    acm.ac_rhs(N, None, y, T, d1)
+    assert torch.equal(d1, d2)
+    del d1
+    j1 = torch.empty_like(j2)
+    acm.ac_jac(N, None, y, T, j1)
+    assert torch.equal(j1, j2)
+    del j1
+    idx = _sample(C, 48, seed=5)
+    assert len(idx) >= 48
+    ii = torch.from_numpy(idx).cuda()
+    ref, ab = oracle_mod.rhs(net, cells.y0[idx], cells.T[idx], with_abs=True)
+    _close(d2[ii].cpu().numpy(), ref, ab)
+    jv = j2[ii].cpu().numpy()
+    for s in range(0, len(idx), 16):
+        sl = slice(s, s + 16)
+        J, abJ = oracle_mod.jac_dense(net, cells.y0[idx[sl]], cells.T[idx[sl]], with_abs=True)
+        _close(jv[sl], _jac_at_pattern(N, J), _jac_at_pattern(N, abJ))

@@ -86,7 +86,7 @@ def test_integration_full_size_sampled(acm, torch_dev, oracle_mod, medium_net):
     assert steps.max() == 200 and bool(torch.isfinite(y).all())
     idx = _sample(C, 4)
     ref, env, _ = oracle_with_envelope(oracle_mod, net, cells.y0[idx], cells.T[idx], 1e6 * YEAR_S,
-                                       k=2, max_steps=200)
+                                       k=8, max_steps=200)
     assert st[idx].tolist() == ref["status"].tolist()
     ok = _agree(y.cpu().numpy()[idx], ref["y"], envelope=env)
     assert ok.all(), np.argwhere(~ok)[:5]

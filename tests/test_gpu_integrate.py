@@ -108,27 +108,29 @@ def _agree(y_gpu, y_ora, rtol=1e-6, floor=1e-20, envelope=None):
     return (np.abs(y_gpu - y_ora) <= tol) | (np.maximum(np.abs(y_gpu), np.abs(y_ora)) < floor)
 
 
-def oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=4, **kw):
+def oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=8, **kw):
     """Oracle run plus the spread of k reruns with y0 perturbed by 1e-15 and
     the rate prefactors alpha by 1e-14 relative: the trajectory's own
     sensitivity to rounding of the size by which the two sides' rate
     coefficients differ (exp of a sum against the product of a power and
-    an exp, up to ~100 ulp)."""
+    an exp, up to ~100 ulp). The k + 1 oracle calls run concurrently (each
+    releases the interpreter lock while it integrates)."""
+    import concurrent.futures as cf
     import dataclasses
     y0 = np.atleast_2d(y0)
-    n = y0.shape[0]
     T = np.atleast_1d(T)
-    ref = oracle_mod.bdf(net, y0, T, t_end, **kw)
     rng = np.random.default_rng(12345)
-    ys, steps = [ref["y"]], [ref["stats"][:, 0]]
+    jobs = [(net, y0)]
     for _ in range(k):
         pnet = dataclasses.replace(net, alpha=net.alpha * (1 + 1e-14 * rng.standard_normal(net.alpha.shape)))
-        o = oracle_mod.bdf(pnet, y0 * (1 + 1e-15 * rng.standard_normal(y0.shape)), T, t_end, **kw)
-        ys.append(o["y"])
-        steps.append(o["stats"][:, 0])
-    ys = np.stack(ys)
+        jobs.append((pnet, y0 * (1 + 1e-15 * rng.standard_normal(y0.shape))))
+    with cf.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        outs = list(ex.map(lambda j: oracle_mod.bdf(j[0], j[1], T, t_end, **kw), jobs))
+    ref = outs[0]
+    ys = np.stack([o["y"] for o in outs])
+    steps = np.stack([o["stats"][:, 0] for o in outs])
     env = np.abs(ys[1:] - ys[0]).max(0)
-    return ref, env, np.stack(steps)
+    return ref, env, steps
 
 
 def _run(acm, torch, net, y0, T, t_end, ws=None, **kw):
@@ -173,20 +175,35 @@ def test_tiny_network_parity(acm, torch_dev, oracle_mod, tiny, q_max, years):
     assert np.all((g >= lo - slack) & (g <= hi + slack))
 
 
+# Floor for the fraction of species-cells that meet the strict bar in a
+# free-running integration of the paper-sized network (the rest must lie
+# within 10x the oracle's own rerun spread). The strict bar itself is met
+# element by element when both sides follow one step sequence
+# (test_gpu_strict.py).
+STRICT_FLOOR_MEDIUM = 0.95
+
+
 def test_medium_network_parity(acm, torch_dev, oracle_mod, medium):
-    """Paper-sized network (470 species / 4600 reactions), BDF 1-5 to 1e6 yr."""
+    """Paper-sized network (470 species / 4600 reactions), BDF 1-5 to 1e6 yr,
+    free running on both sides; 8 perturbed oracle reruns set the envelope."""
     torch = torch_dev
     net, cells = medium
     idx = [0, 5, 9]
     y0, T = cells.y0[idx], cells.T[idx]
     t_end = 1e6 * YEAR_S
     y, out, _ = _run(acm, torch, net, y0, T, t_end)
-    ref, env, steps = oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=2)
+    ref, env, steps = oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=8)
     assert out["status"].tolist() == ref["status"].tolist() == [0] * len(idx)
     bad = ~_agree(y, ref["y"], envelope=env)
     assert not bad.any(), (np.argwhere(bad)[:5], out["stats"], ref["stats"])
-    print(f"strict 1e-6 bar met by {_agree(y, ref['y']).mean():.4f} of species-cells;",
-          "steps gpu", out["stats"][:, 0].tolist(), "oracle", steps.tolist())
+    strict = _agree(y, ref["y"])
+    only_env = np.argwhere(~strict)
+    names = [f"cell {idx[c]}: {net.names[i]} (gpu {y[c, i]:.6e}, oracle {ref['y'][c, i]:.6e}, "
+             f"spread {env[c, i]:.1e})" for c, i in only_env[:20]]
+    print(f"strict 1e-6 bar met by {strict.mean():.4f} of species-cells; "
+          f"{len(only_env)} pass only through the envelope:", *names, sep="\n  ")
+    print("steps gpu", out["stats"][:, 0].tolist(), "oracle reruns", steps.T.tolist())
+    assert strict.mean() >= STRICT_FLOOR_MEDIUM
     assert np.all(np.abs(out["stats"][:, 0] - ref["stats"][:, 0]) <= 0.02 * ref["stats"][:, 0] + 3)
     E = net.composition.astype(np.float64).T
     drift = np.abs(y @ E.T - y0 @ E.T) / (y0 @ np.abs(E).T)
@@ -203,7 +220,7 @@ def test_large_network_parity(acm, torch_dev, oracle_mod):
     y0, T = cells.y0[:1], cells.T[:1]
     t_end = 1e2 * YEAR_S
     y, out, _ = _run(acm, torch, net, y0, T, t_end)
-    ref, env, steps = oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=2)
+    ref, env, steps = oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=8)
     assert out["status"].tolist() == ref["status"].tolist() == [0]
     ok = _agree(y, ref["y"], envelope=env)
     assert ok.all(), np.argwhere(~ok)[:5]
@@ -262,27 +279,44 @@ def _tape_compare(a_tape, a_len, b_tape, b_len):
     return abs(a_len - b_len), prefix / m, np.median(rel), np.quantile(rel, 0.95)
 
 
-def test_recorded_tape_matches_oracle(acm, torch_dev, oracle_mod, tiny):
+@pytest.mark.parametrize("which", ["tiny", "medium"])
+def test_recorded_tape_matches_oracle(acm, torch_dev, oracle_mod, tiny, medium_net, which):
     """The recorded step sequence (used by replay and the adjoint) carries the
     oracle's decisions and values to within the oracle's own sensitivity:
     each statistic of the GPU tape against the oracle's is bounded by the
-    worst that 8 oracle reruns with y0 perturbed by 1e-15 relative show."""
+    worst that 8 oracle reruns with y0 perturbed by 1e-15 and alpha by 1e-14
+    relative show. The 50-species network to 1e5 yr, and the paper-sized
+    network (first 2 cells of the 16,384-cell workload) to 1e6 yr."""
+    import concurrent.futures as cf
+    import dataclasses
     torch = torch_dev
-    net, cells = tiny
-    y0, T = cells.y0[:2], np.array([20.0, 90.0])
-    t_end = 1e5 * YEAR_S
-    _, out, raw = _run(acm, torch, net, y0, T, t_end, tape_cap=20000)
+    if which == "tiny":
+        net, cells = tiny
+        y0, T = cells.y0[:2], np.array([20.0, 90.0])
+        t_end, cap = 1e5 * YEAR_S, 20000
+    else:
+        net = medium_net
+        cells = synthnet.make_cells(net, 16384, synthnet.SEED_BASE + 2)
+        y0, T = cells.y0[:2].copy(), cells.T[:2].copy()
+        t_end, cap = 1e6 * YEAR_S, 40000
+    _, out, raw = _run(acm, torch, net, y0, T, t_end, tape_cap=cap)
     tape = acm.tape_to_numpy(raw["tape"])
-    ref = oracle_mod.bdf(net, y0, T, t_end, tape_cap=20000)
     rng = np.random.default_rng(99)
-    pert = [oracle_mod.bdf(net, y0 * (1 + 1e-15 * rng.standard_normal(y0.shape)), T, t_end,
-                           tape_cap=20000) for _ in range(8)]
+    jobs = [(net, y0)]
+    for _ in range(8):
+        pnet = dataclasses.replace(net, alpha=net.alpha * (1 + 1e-14 * rng.standard_normal(net.alpha.shape)))
+        jobs.append((pnet, y0 * (1 + 1e-15 * rng.standard_normal(y0.shape))))
+    with cf.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        runs = list(ex.map(lambda j: oracle_mod.bdf(j[0], j[1], T, t_end, tape_cap=cap), jobs))
+    ref, pert = runs[0], runs[1:]
     for c in range(2):
         Lo = int(ref["tape_len"][c])
+        assert Lo > 0 and int(out["tape_len"][c]) > 0
         g = _tape_compare(tape[c], int(out["tape_len"][c]), ref["tape"][c], Lo)
         p = np.array([_tape_compare(o["tape"][c], int(o["tape_len"][c]), ref["tape"][c], Lo)[:4]
                       for o in pert])
-        print(f"cell {c}: gpu dlen {g[0]} prefix {g[1]:.3f} median {g[2]:.2e} q95 {g[3]:.2e};",
+        print(f"{which} cell {c}: events gpu {int(out['tape_len'][c])} oracle {Lo}; gpu dlen {g[0]} "
+              f"prefix {g[1]:.3f} median {g[2]:.2e} q95 {g[3]:.2e};",
               f"perturbed worst dlen {p[:, 0].max():.0f} prefix {p[:, 1].min():.3f}",
               f"median {p[:, 2].max():.2e} q95 {p[:, 3].max():.2e}")
         assert g[0] <= p[:, 0].max() + 1

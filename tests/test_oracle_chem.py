@@ -1,5 +1,6 @@
 """Pins of the oracle's rate, RHS, Jacobian and VJP against facts fixed by
 the paper and by mathematics (not against the oracle itself)."""
+import dataclasses
 import json
 import os
 
@@ -151,6 +152,68 @@ def test_rate_coefficient_log_derivative(oracle_mod, medium_net):
     fd = (np.log(kp) - np.log(km)) / (2 * e)
     ref = net.beta[None, :] + net.gamma[None, :] / T[:, None]
     assert np.all(np.abs(fd - ref) <= 1e-6 * (1 + np.abs(ref)))
+
+
+def _law_net(laws, alpha, beta, gamma):
+    rx = [([0], [1])] * len(laws)
+    net = network_from(rx, alpha, 2, beta=beta, gamma=gamma)
+    net.law = np.asarray(laws, np.int8)
+    return net
+
+
+def test_rate_laws_special_cases(oracle_mod):
+    """Reference conditions recover the tabulated prefactor: direct
+    cosmic-ray ionisation at zeta = zeta_0 gives alpha; an FUV photorate
+    with no extinction (A_V = 0) in the unit field (G_0 = 1) gives alpha;
+    the cosmic-ray photon law at T = 300 K, zeta = zeta_0 gives alpha gamma
+    / (1 - albedo) with albedo 0.6; the modified Arrhenius law ignores A_V,
+    zeta and G_0."""
+    L = oracle_mod
+    net = _law_net([L.LAW_CRP, L.LAW_PHOTO, L.LAW_CRPHOT, L.LAW_KOOIJ], [2e-17, 3e-10, 1.3e-17, 4e-10],
+                   [0.7, 0.0, 0.3, 0.5], [9.0, 2.5, 800.0, 120.0])
+    cond = np.array([[300.0, 0.0, 1.0, 1.0], [40.0, 3.0, 7.0, 25.0]])
+    k = L.rate_coeffs(net, cond)
+    assert k[0, 0] == 2e-17 and k[0, 1] == 3e-10
+    assert abs(k[0, 2] / (1.3e-17 * 800.0 * 2.5) - 1) < 1e-15
+    kooij = L.rate_coeffs(network_from([([0], [1])], [4e-10], 2, beta=[0.5], gamma=[120.0]),
+                          [300.0, 40.0])
+    assert k[0, 3] == kooij[0, 0] and k[1, 3] == kooij[1, 0]
+
+
+def test_rate_laws_scalings(oracle_mod):
+    """Cosmic-ray rates are linear in zeta and photorates in G_0 (doubling is
+    exact in floating point); one magnitude of extinction divides a photorate
+    by exp(gamma); the cosmic-ray photon law scales with T like (T/300)^beta."""
+    L = oracle_mod
+    net = _law_net([L.LAW_CRP, L.LAW_CRPHOT, L.LAW_PHOTO], [2e-17, 1.3e-17, 3e-10],
+                   [0.0, 0.4, 0.0], [0.0, 500.0, 1.8])
+    base = np.array([[55.0, 2.0, 0.8, 3.0]])
+    k0 = L.rate_coeffs(net, base)[0]
+    z2 = base.copy(); z2[0, 2] *= 2
+    g2 = base.copy(); g2[0, 3] *= 2
+    a1 = base.copy(); a1[0, 1] += 1.0
+    t2 = base.copy(); t2[0, 0] *= 2
+    kz, kg, ka, kt = (L.rate_coeffs(net, c)[0] for c in (z2, g2, a1, t2))
+    assert kz[0] == 2 * k0[0] and kz[1] == 2 * k0[1] and kz[2] == k0[2]
+    assert kg[2] == 2 * k0[2] and kg[0] == k0[0] and kg[1] == k0[1]
+    assert abs(k0[2] / ka[2] - np.exp(1.8)) < 1e-14 * np.exp(1.8)
+    assert abs(kt[1] / k0[1] - 2 ** 0.4) < 1e-14 and kt[0] == k0[0] and kt[2] == k0[2]
+
+
+def test_rate_laws_typed_network_rhs(oracle_mod, medium_net):
+    """On the paper-sized network with cosmic-ray and photo laws on its
+    one-body reactions, the RHS of every cell still conserves elements and
+    charge (E f = 0), and a Kooij-only network reproduces the plain
+    temperature-only call bit for bit."""
+    net = synthnet.with_rate_laws(medium_net, 5)
+    cells = synthnet.make_cells(net, 6, synthnet.SEED_BASE + 9)
+    cond = synthnet.make_conditions(cells.T, 9)
+    f, ab = oracle_mod.rhs(net, cells.y0, cond, with_abs=True)
+    E = net.composition.astype(np.float64).T
+    assert np.all(np.abs(f @ E.T) <= 1e-12 * (ab @ np.abs(E).T) + 1e-300)
+    plain = oracle_mod.rhs(medium_net, cells.y0, cells.T)
+    kooij = dataclasses.replace(medium_net, law=np.zeros(medium_net.n_reactions, np.int8))
+    assert np.array_equal(oracle_mod.rhs(kooij, cells.y0, cond), plain)
 
 
 # --------------------------------------------------------------- Jacobian
