@@ -42,13 +42,20 @@ def parse():
     p.add_argument("--no-table", action="store_true",
                    help="skip the autotuner (layout x ordering x block table); use sell/nnz/512")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--cpu-seconds", type=float, default=20.0,
+                   help="about this many seconds per thread setting (five repeats)")
     p.add_argument("--no-int", action="store_true", help="skip the integration legs")
-    p.add_argument("--int-cells", type=int, default=2048, help="cells of the batched integration leg")
-    p.add_argument("--int-max-steps", type=int, default=20000)
-    p.add_argument("--plain-cells", type=int, default=2, help="cells timed through the plain loop")
-    p.add_argument("--adj-cells", type=int, default=256)
-    p.add_argument("--adj-max-steps", type=int, default=1500)
+    p.add_argument("--int-cells", type=int, default=16384,
+                   help="cells of the batched integration leg (the 16,384-cell workload)")
+    p.add_argument("--int-max-steps", type=int, default=20000,
+                   help="accepted-step budget per cell (batched and plain alike)")
+    p.add_argument("--int-chunks", type=int, default=8,
+                   help="launches the batched leg is split into (two streams, so a chunk's "
+                        "slots are taken over by the next chunk's cells as they free up)")
+    p.add_argument("--plain-cells", type=int, default=64, help="cells timed through the plain loop")
+    p.add_argument("--adj-cells", type=int, default=256,
+                   help="cells of the adjoint leg (first cells of the 4,096-cell workload)")
+    p.add_argument("--adj-max-steps", type=int, default=20000)
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain device copy of the densities (known bytes) so HBM "
                         "counters can be calibrated in the same profile")
@@ -75,35 +82,59 @@ class Timer:
         return float(np.mean([a.elapsed_time(b) for a, b in self.ev[name]]))
 
 
-def cpu_baseline(net, cells, seconds):
-    """The oracle (plain C, FP64, OpenMP over cells) on a bounded sample."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(net, cells, seconds, pattern):
+    """The oracle (plain C, FP64, OpenMP over cells) computing what one GPU
+    step computes: the RHS and the Jacobian's values on the same pattern
+    (nnz_j entries per cell), on a bounded sample of the same cells. Five
+    timed repeats on one thread and on every host thread; value = the
+    all-thread mean."""
     import oracle
+    rp, col = pattern
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     threads = max(1, min(threads, os.cpu_count() or 1))
-    oracle.set_threads(threads)
-    # size the sample from a short probe so the run takes about `seconds`
-    probe = min(64, cells.T.size)
-    t0 = time.perf_counter()
-    oracle.rhs(net, cells.y0[:probe], cells.T[:probe])
-    oracle.jac_dense(net, cells.y0[:probe], cells.T[:probe])
-    dt = max(time.perf_counter() - t0, 1e-6)
-    n = int(min(cells.T.size, max(probe, probe * seconds / dt)))
-    # whole passes over the sample until about `seconds` have elapsed
-    t0 = time.perf_counter()
-    passes = 0
-    while True:
-        for s in range(0, n, 256):
-            e = min(n, s + 256)
+
+    def one_pass(n):
+        for s in range(0, n, 512):
+            e = min(n, s + 512)
             oracle.rhs(net, cells.y0[s:e], cells.T[s:e])
-            oracle.jac_dense(net, cells.y0[s:e], cells.T[s:e])
-        passes += 1
-        dt = time.perf_counter() - t0
-        if dt >= seconds or n < cells.T.size:
-            break
-    return {"value": passes * n * net.n_reactions / dt, "unit": "cell-reactions/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"RHS + dense Jacobian of the first {n} of the {cells.T.size} cells, "
-                      f"{passes} pass(es) in {dt:.1f} s on {threads} threads"}
+            oracle.jac_pattern(net, cells.y0[s:e], cells.T[s:e], rp, col)
+
+    res = {}
+    for label, th in (("1_thread", 1), ("all_threads", threads)):
+        oracle.set_threads(th)
+        probe = min(64 * th, cells.T.size)
+        t0 = time.perf_counter()
+        one_pass(probe)
+        dt = max(time.perf_counter() - t0, 1e-6)
+        # five repeats of about seconds / 10 each
+        n = int(min(cells.T.size, max(probe, probe * seconds / 10 / dt)))
+        rates = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            one_pass(n)
+            rates.append(n * net.n_reactions / (time.perf_counter() - t0))
+        r = np.array(rates)
+        res[label] = {"threads": th, "cells": n, "mean": float(r.mean()),
+                      "se": float(r.std(ddof=1) / np.sqrt(len(r)))}
+    a = res["all_threads"]
+    return {"value": a["mean"], "unit": "cell-reactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"RHS + Jacobian on the GPU's pattern ({len(col)} values per cell) of the "
+                      f"first {a['cells']} of the {cells.T.size} cells, 5 timed repeats on "
+                      f"{threads} threads (mean {a['mean']:.3e} +- {a['se']:.1e} SE); one "
+                      f"thread: first {res['1_thread']['cells']} cells, "
+                      f"{res['1_thread']['mean']:.3e} +- {res['1_thread']['se']:.1e}",
+            "cpu_model": _cpu_model(), "host_threads": os.cpu_count(),
+            "one_thread": res["1_thread"], "all_threads": a}
 
 
 # Sources that make up the fused RHS + Jacobian kernel: the HBM traffic
@@ -186,92 +217,163 @@ def lu_leg(torch, acm, net, cells, n_mat=256):
                    "solve_hbm_frac": sbytes / (sv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
-def integration_legs(args, torch, acm, net, cells):
-    """Batched BDF (one persistent workgroup per slot, device cell queue)
-    on the first --int-cells cells against the plain per-cell loop timed on
-    the first --plain-cells of them; then the discrete adjoint of a shorter
-    run on --adj-cells cells. Wall-clock timing (synchronised)."""
-    dev = torch.device("cuda:0")
-    N = acm.Network.from_synth(net)
-    ws = acm.Workspace(N)
-    t_end = 1e6 * YEAR_S
-    res = {}
-    n = min(args.int_cells, cells.T.size)
-    y = torch.from_numpy(cells.y0[:n].copy()).to(dev)
-    T = torch.from_numpy(cells.T[:n].copy()).to(dev)
+def _integrate_chunked(torch, acm, wss, y, T, t_end, max_steps, nch, label):
+    """Batched integration of every cell, split into nch launches issued
+    back to back alternately on two streams with a workspace each: the
+    persistent workgroups of a chunk take cells from its own queue and a
+    later chunk's workgroups start on the compute units the earlier ones
+    free, so the split costs no idle tail. Prints a line as each chunk
+    completes. Returns (wall seconds, stats, status)."""
+    C = y.shape[0]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = ws.integrate(y, T, t_end, max_steps=args.int_max_steps)
+    outs, evs = [], []
+    for k in range(nch):
+        s = slice(k * C // nch, (k + 1) * C // nch)
+        st = streams[k % 2]
+        with torch.cuda.stream(st):
+            o = wss[k % 2].integrate(y[s], T[s], t_end, max_steps=max_steps, stream=st.cuda_stream)
+            e = torch.cuda.Event()
+            e.record(st)
+        outs.append(o)
+        evs.append(e)
+    for k, e in enumerate(evs):
+        e.synchronize()
+        print(f"[bench] {label}: chunk {k + 1}/{nch} done at {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    st = out["stats"].cpu().numpy()
-    status = out["status"].cpu().numpy()
+    st = np.concatenate([o["stats"].cpu().numpy() for o in outs])
+    status = np.concatenate([o["status"].cpu().numpy() for o in outs])
+    return wall, st, status
+
+
+def integration_legs(args, torch, acm, net):
+    """Integrated cells/s of the batched BDF on the 16,384-cell workload (470 /
+    4600 network, T log-uniform on 10-300 K, n_H log-uniform on 1e2-1e7,
+    BDF 1-5 to 1e6 yr, rtol 1e-6, atol 1e-20), the plain one-cell-per-launch
+    loop timed on the first --plain-cells of the same cells under the same
+    step budget (and the batched kernel on those same cells), then the
+    discrete adjoint of --adj-cells cells of the 4,096-cell workload to
+    t_end. Wall-clock timing, synchronised."""
+    import synthnet
+    dev = torch.device("cuda:0")
+    N = acm.Network.from_synth(net)
+    wss = [acm.Workspace(N), acm.Workspace(N)]
+    t_end = 1e6 * YEAR_S
+    K = args.int_max_steps
+    res = {}
+    cells = synthnet.make_cells(net, args.int_cells, synthnet.SEED_BASE + 2)
+    n = cells.T.size
+    y = torch.from_numpy(cells.y0.copy()).to(dev)
+    T = torch.from_numpy(cells.T.copy()).to(dev)
+    wall, st, status = _integrate_chunked(torch, acm, wss, y, T, t_end, K, args.int_chunks,
+                                          f"batched integration of {n} cells")
     steps = int(st[:, 0].sum())
     ok = int((status == 0).sum())
-    print(f"[bench] batched integration: {n} cells in {wall:.1f} s", file=sys.stderr, flush=True)
+    capped = np.flatnonzero(status == 1)
+    # the plain loop and the batched kernel on the same first cells
     npl = min(args.plain_cells, n)
-    yp = torch.from_numpy(cells.y0[:npl].copy()).to(dev)
+    yb = torch.from_numpy(cells.y0[:npl].copy()).to(dev)
     Tp = torch.from_numpy(cells.T[:npl].copy()).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    outp = ws.integrate(yp, Tp, t_end, max_steps=args.int_max_steps, plain=True)
+    ob = wss[0].integrate(yb, Tp, t_end, max_steps=K)
     torch.cuda.synchronize()
-    wall_p = time.perf_counter() - t0
-    steps_p = int(outp["stats"].cpu().numpy()[:, 0].sum())
-    plain_sps = steps_p / wall_p
-    plain_wall_est = steps / plain_sps
-    print(f"[bench] plain integration: {npl} cells in {wall_p:.1f} s", file=sys.stderr, flush=True)
+    wall_b = time.perf_counter() - t0
+    wall_p, sp, stp, same = 0.0, [], [], True
+    for k in range(0, npl, 8):
+        yp = torch.from_numpy(cells.y0[k:k + 8].copy()).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op = wss[0].integrate(yp, Tp[k:k + 8], t_end, max_steps=K, plain=True)
+        torch.cuda.synchronize()
+        wall_p += time.perf_counter() - t0
+        sp.append(op["stats"].cpu().numpy())
+        stp.append(op["status"].cpu().numpy())
+        same = same and bool(torch.equal(yp, yb[k:k + 8]))
+        print(f"[bench] plain loop: {min(k + 8, npl)}/{npl} cells, {wall_p:.1f} s", file=sys.stderr,
+              flush=True)
+    sp, stp = np.concatenate(sp), np.concatenate(stp)
+    ok_p = int((stp == 0).sum())
     res["integration"] = {
-        "workload": f"470/4600 network, first {n} of the {cells.T.size} cells, BDF 1-5 to 1e6 yr, "
-                    f"rtol 1e-6, atol 1e-20, max_steps {args.int_max_steps}",
+        "workload": f"470/4600 network, {n} cells (T log-uniform 10-300 K, n_H log-uniform "
+                    f"1e2-1e7 cm^-3), BDF 1-5 to 1e6 yr, rtol 1e-6, atol 1e-20, "
+                    f"max_steps {K} per cell",
         "cells": n, "wall_s": wall, "cells_reaching_t_end": ok,
-        "cells_maxsteps": int((status == 1).sum()),
-        "integrated_cells_per_s": ok / wall,
+        "cells_maxsteps": int(capped.size), "first_capped_cells": capped[:16].tolist(),
+        "integrated_cells_per_s": ok / wall, "cells_per_s_all": n / wall,
         "steps": steps, "steps_per_s": steps / wall,
-        "step_quantiles_10_50_90_max": np.quantile(st[:, 0], [0.1, 0.5, 0.9, 1.0]).tolist(),
+        "step_quantiles_10_50_90_99_max": np.quantile(st[:, 0], [0.1, 0.5, 0.9, 0.99, 1.0]).tolist(),
         "newton_iters_per_step": float(st[:, 3].sum() / max(steps, 1)),
         "lu_per_step": float(st[:, 5].sum() / max(steps, 1)),
-        "slots": ws.n_slots,
-        "plain": {"cells": npl, "wall_s": wall_p, "steps": steps_p, "steps_per_s": plain_sps,
-                  "est_wall_s_same_cells": plain_wall_est,
-                  "est_integrated_cells_per_s": ok / plain_wall_est,
-                  "note": "plain = one cell per launch through the same kernel; its time for "
-                          "the batched sample is estimated from its measured steps/s times the "
-                          "sample's step count"},
-        "vs_plain": plain_wall_est / wall,
+        "jac_per_step": float(st[:, 4].sum() / max(steps, 1)),
+        "rejections_per_step": float((st[:, 1] + st[:, 2]).sum() / max(steps, 1)),
+        "slots": wss[0].n_slots, "launches": args.int_chunks,
+        "plain": {"cells": npl, "wall_s": wall_p, "cells_reaching_t_end": ok_p,
+                  "integrated_cells_per_s": ok_p / wall_p, "steps": int(sp[:, 0].sum()),
+                  "steps_per_s": float(sp[:, 0].sum() / wall_p),
+                  "batched_wall_s_same_cells": wall_b,
+                  "same_results_as_batched": same,
+                  "note": "plain = the same kernel launched once per cell with one workgroup, "
+                          "launches issued back to back; timed on the first cells of the "
+                          "workload under the same step budget"},
+        "vs_plain": (ok / wall) / (ok_p / wall_p) if ok_p else None,
+        "vs_plain_same_cells": wall_p / wall_b,
     }
     # discrete adjoint: forward with tape, then the timed adjoint sweep
-    na = min(args.adj_cells, cells.T.size)
-    ya = torch.from_numpy(cells.y0[:na].copy()).to(dev)
-    Ta = torch.from_numpy(cells.T[:na].copy()).to(dev)
+    acells = synthnet.make_cells(net, 4096, synthnet.SEED_BASE + 3)
+    na = min(args.adj_cells, 4096)
+    ya = torch.from_numpy(acells.y0[:na].copy()).to(dev)
+    Ta = torch.from_numpy(acells.T[:na].copy()).to(dev)
     cap = 2 * args.adj_max_steps + 64
-    fw = ws.integrate(ya, Ta, t_end, max_steps=args.adj_max_steps, tape_cap=cap)
-    rng = np.random.default_rng(8)
-    tgt = rng.choice(net.n_species, 8, replace=False)
-    lam = torch.zeros_like(ya)
-    lam[:, tgt] = 1.0 / ya[:, tgt].clamp_min(1e-30)
-    y0a = torch.from_numpy(cells.y0[:na].copy()).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    adj = ws.adjoint(y0a, Ta, fw["tape"], fw["tape_len"], lam)
+    fw = wss[0].integrate(ya, Ta, t_end, max_steps=args.adj_max_steps, tape_cap=cap)
+    torch.cuda.synchronize()
+    wall_f = time.perf_counter() - t0
+    print(f"[bench] adjoint forward: {na} cells in {wall_f:.1f} s", file=sys.stderr, flush=True)
+    yT = ya.cpu().numpy()
+    rng = np.random.default_rng(8)
+    lam = np.zeros_like(yT)
+    for c in range(na):
+        okc = np.flatnonzero(yT[c] > 1e-20)
+        tgt = rng.choice(okc, 8, replace=False)
+        lam[c, tgt] = 1.0 / yT[c, tgt]
+    y0a = torch.from_numpy(acells.y0[:na].copy()).to(dev)
+    # the tapes cut to the longest one, and room for every converged state
+    # reserved before the timed region
+    L = int(fw["tape_len"].max().item()) + 1
+    tape = fw["tape"][:, :L].contiguous()
+    wss[0].reserve_adjoint(L, keep_states=True, max_cells=na)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    adj = wss[0].adjoint(y0a, Ta, tape, fw["tape_len"], torch.from_numpy(lam).to(dev))
     torch.cuda.synchronize()
     wall_a = time.perf_counter() - t0
+    fst = fw["status"].cpu().numpy()
     sa = int(fw["stats"].cpu().numpy()[:, 0].sum())
     ast_ = adj["stats"].cpu().numpy()
     print(f"[bench] adjoint: {na} cells in {wall_a:.1f} s", file=sys.stderr, flush=True)
     res["adjoint"] = {
-        "workload": f"470/4600 network, first {na} cells, d sum log y_t / d (log alpha, y0) for 8 "
-                    f"seeded targets through BDF capped at {args.adj_max_steps} steps per cell "
-                    f"(t_end 1e6 yr), checkpoints every 64 steps",
-        "cells": na, "wall_s": wall_a, "cells_per_s": na / wall_a, "steps": sa,
+        "workload": f"470/4600 network, first {na} of the 4,096-cell workload, d sum log y_t / "
+                    f"d (log alpha, y0) for 8 seeded targets per cell, BDF 1-5 to 1e6 yr "
+                    f"(max_steps {args.adj_max_steps}), checkpoints every 64 steps, every "
+                    f"converged state kept",
+        "cells": na, "forward_wall_s": wall_f, "wall_s": wall_a,
+        "forward_plus_adjoint_s": wall_f + wall_a, "cells_per_s": na / (wall_f + wall_a),
+        "cells_reaching_t_end": int((fst == 0).sum()), "steps": sa,
         "adjoint_steps_per_s": sa / wall_a,
         "status_ok": int((adj["status"] == 0).sum().item()),
+        "states_kept": wss[0].keeps_states, "tape_events_max": L,
         "per_step": {"replay_newton_iters": float(ast_[:, 3].sum() / max(sa, 1)),
                      "jacobians": float(ast_[:, 4].sum() / max(sa, 1)),
                      "factorisations": float(ast_[:, 5].sum() / max(sa, 1)),
                      "rhs": float(ast_[:, 6].sum() / max(sa, 1))},
     }
-    ws.close()
+    for w in wss:
+        w.close()
     return res
 
 
@@ -416,9 +518,9 @@ def main():
     }
     if not args.no_int:
         out.update(lu_leg(torch, acm, net, cells))
-        out.update(integration_legs(args, torch, acm, net, cells))
+        out.update(integration_legs(args, torch, acm, net))
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(net, cells, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(net, cells, args.cpu_seconds, N.jac_pattern())
     print(json.dumps(out))
 
 

@@ -58,9 +58,13 @@ typedef enum {
 typedef enum {
   AC_CELL_OK = 0,
   AC_CELL_MAXSTEPS = 1,   /* step budget exhausted before t_end */
-  AC_CELL_HMIN = 2,       /* step size fell below 10 ulp(t) */
+  AC_CELL_HMIN = 2,       /* step size fell below 10 ulp(t) after error-test rejections */
   AC_CELL_BADINPUT = 3,   /* T <= 0 or not finite, or an initial density < 0 or not finite */
-  AC_CELL_TAPE = 4        /* adjoint: the cell's tape overflowed or is malformed */
+  AC_CELL_TAPE = 4,       /* adjoint: the cell's tape overflowed or is malformed */
+  AC_CELL_NEWTON_FAIL = 5,/* step size fell below 10 ulp(t): the corrector iteration kept
+                             failing to converge (on finite values) */
+  AC_CELL_SINGULAR = 6,   /* ... the last Newton matrix had an exactly zero pivot */
+  AC_CELL_NONFINITE = 7   /* ... the RHS kept producing non-finite values */
 } ac_cell_status;
 
 /* Storage of S used by the RHS kernel (Sec. 2.2 compares COO, CCS, CRS and
@@ -131,6 +135,9 @@ typedef struct {
                                 or 1024; 0 = default (512) */
   const int8_t *rate_law;    /* host [n_reactions] ac_rate_law codes, or NULL (every reaction
                                 AC_LAW_KOOIJ, per-cell conditions = T only) */
+  const double *heat;        /* host [n_reactions] energy released per reaction event [erg]
+                                (exothermic > 0) for the temperature-coupled calls, or NULL
+                                (no chemical heating) */
 } ac_net_desc;
 
 typedef struct ac_net ac_net;
@@ -221,6 +228,27 @@ ac_status ac_vjp(const ac_net *net, const double *log_alpha, int64_t n_cells, co
                  const double *T, const double *v, double *gy, double *g_logalpha,
                  ac_stream stream);
 
+/* ------------------------------------------- temperature as a state
+ * Codes that solve temperature and abundances together within the stiff
+ * solver (Sec. 5) make T part of the state. Per cell the state is
+ * (n_1..n_ns, T): y and dydt are [n_cells][n_species + 1]; the rate
+ * coefficients follow the state's T (the T column of the conditions array
+ * is not read; A_V, zeta and G_0 are) and
+ *     dT/dt = (sum_j heat_j R_j) / c_v - lambda (T - T_b)
+ * with therm [n_cells][3] = (c_v [erg cm^-3 K^-1] > 0, T_b [K] > 0,
+ * lambda [1/s] >= 0) per cell and heat_j from the network description.
+ * ac_jac_thermal writes per cell nnz_j + 2 n_species + 1 values: the
+ * pattern values (as ac_jac, at the state's T), the T column
+ * d(dn_i/dt)/dT = sum_j S_ij R_j d ln k_j/dT, the T row
+ * d(dT/dt)/dn_a = sum_j heat_j dR_j/dn_a / c_v, and the corner
+ * d(dT/dt)/dT. All pointers DEVICE; errors as ac_rhs. */
+ac_status ac_rhs_thermal(const ac_net *net, const double *log_alpha, int64_t n_cells,
+                         const double *y, const double *T, const double *therm, double *dydt,
+                         ac_stream stream);
+ac_status ac_jac_thermal(const ac_net *net, const double *log_alpha, int64_t n_cells,
+                         const double *y, const double *T, const double *therm, double *jvals,
+                         ac_stream stream);
+
 /* ------------------------------------------------ batched dense LU
  * The Newton matrices of the implicit integrator are dense n x n (n =
  * species), one per cell. A: [n_mat][n][lda] row-major DEVICE array,
@@ -255,10 +283,15 @@ typedef struct {
   double h0;          /* first step [s]; <= 0 selects it (Hairer-Norsett-Wanner) */
   int32_t q_max;      /* 1..5; 1 is adaptive backward Euler */
   int32_t max_steps;  /* accepted-step budget per cell */
-  int32_t adj_recompute; /* adjoint only: 1 recomputes every 64-step segment from
-                            its checkpoint; 0 keeps every converged state of the
-                            forward replay instead when they fit (see
-                            ac_integrate_adjoint) */
+  int32_t adj_recompute; /* adjoint only: 1 recomputes every segment from its
+                            checkpoint; 0 keeps every converged state of the
+                            forward replay instead when the workspace reserved
+                            room for them (see ac_ws_reserve_adjoint) */
+  int32_t checkpoint_every; /* adjoint and replay: accepted steps between
+                            checkpoints; 0 = 64; must equal the interval the
+                            workspace reserved for */
+  double newton_tol;     /* corrector convergence tolerance in the weighted RMS
+                            norm; <= 0 selects max(10 eps/rtol, min(0.03, sqrt(rtol))) */
 } ac_integ_opts;
 
 /* Per-cell counters written by the integrator ([n_cells][AC_NSTAT]). */
@@ -284,6 +317,35 @@ ac_status ac_ws_create(const ac_net *net, int32_t n_slots, ac_ws **out);
 ac_status ac_ws_destroy(ac_ws *ws);
 ac_status ac_ws_info(const ac_ws *ws, int32_t *n_slots, int64_t *bytes);
 
+/* Room for the discrete adjoint and the replay, allocated here (with a
+ * device synchronisation; any earlier reservation is released) so that
+ * ac_integrate_adjoint and ac_replay allocate nothing:
+ *   max_tape          longest tape (events) the calls will pass (tape_cap)
+ *   checkpoint_every  accepted steps between checkpoints; 0 = 64; the calls
+ *                     must use the same interval
+ *   keep_states       1: also room for every converged state of a max_tape
+ *                     replay per slot, when that comes to at most 32 GiB over
+ *                     all slots (max_tape n_species 8 bytes per slot), so the
+ *                     reverse sweep reads them instead of recomputing segments
+ *   max_cells         cells whose per-cell dL/dlog alpha rows the workspace
+ *                     holds, so the summed gradient needs no caller buffer
+ *                     (longer calls run in chunks of max_cells); 0 = none
+ * Per slot: (max_tape / checkpoint_every + 1) 64 n_species bytes of
+ * checkpoints, 8 n_species bytes of adjoint state and checkpoint_every (or,
+ * keeping states, max_tape) 8 n_species bytes of converged states; plus
+ * 8 n_reactions max_cells bytes of rows. */
+typedef struct {
+  int32_t max_tape;
+  int32_t checkpoint_every;
+  int32_t keep_states;
+  int32_t max_cells;
+} ac_adj_reserve;
+ac_status ac_ws_reserve_adjoint(ac_ws *ws, const ac_adj_reserve *r);
+/* What the workspace reserved (zeros when nothing): the longest tape, the
+ * checkpoint interval, whether every state is kept, the gradient rows. */
+ac_status ac_ws_adjoint_info(const ac_ws *ws, int32_t *max_tape, int32_t *checkpoint_every,
+                             int32_t *keeps_states, int32_t *max_cells);
+
 /* Integrates dy/dt = S R(y) from t = 0 to t_end for every cell, T held
  * fixed per cell. y [n_cells][n_species] DEVICE, overwritten with y(t_end)
  * (cells with AC_CELL_BADINPUT are left untouched); T [n_cells] DEVICE.
@@ -297,6 +359,19 @@ ac_status ac_integrate(ac_ws *ws, const double *log_alpha, int64_t n_cells, doub
                        const double *T, double t_end, const ac_integ_opts *opts,
                        int32_t *cell_status, int32_t *cell_stats, ac_event *tape,
                        int32_t tape_cap, int32_t *tape_len, ac_stream stream);
+
+/* The integrator with temperature as a state (see ac_rhs_thermal): y
+ * [n_cells][n_species + 1] (DEVICE, in/out; initial T > 0 in the last
+ * entry), conditions T and therm [n_cells][3] as there. The Newton matrix is
+ * (n_species + 1)^2 with the T column and row; the coefficients are
+ * recomputed at every RHS and Jacobian evaluation. Same rules, options and
+ * per-cell outputs as ac_integrate (no tape: the adjoint covers the
+ * fixed-temperature integrator). AC_CELL_BADINPUT also for T <= 0 or bad
+ * therm values. */
+ac_status ac_integrate_thermal(ac_ws *ws, const double *log_alpha, int64_t n_cells, double *y,
+                               const double *T, const double *therm, double t_end,
+                               const ac_integ_opts *opts, int32_t *cell_status,
+                               int32_t *cell_stats, ac_stream stream);
 
 /* Same integrator, one cell per kernel launch, one workgroup, launches
  * issued back to back from the host: the unbatched baseline. */
@@ -312,35 +387,32 @@ ac_status ac_integrate_plain(ac_ws *ws, const double *log_alpha, int64_t n_cells
  * step is differentiated through the implicit function theorem: one
  * transposed solve with M = I - c J(y_{n+1}), refactored at the converged
  * state, and one vector-Jacobian product per step. The tape is replayed
- * forward once, keeping the difference array every 64 accepted steps, and
- * each 64-step segment is recomputed from its checkpoint during the
- * reverse sweep. Not in the paper; the forward method is Sec. 3's BDF
+ * forward once, keeping the difference array every checkpoint_every accepted
+ * steps (and every converged state when the workspace has room), and the
+ * reverse sweep reads the kept states or recomputes each segment from its
+ * checkpoint. Not in the paper; the forward method is Sec. 3's BDF
  * integration of eq. matrix-form.
  *   y0, lambda [n_cells][n_species], T [n_cells]    DEVICE, read
  *   tape [n_cells][tape_cap], tape_len [n_cells]    DEVICE, read
  *   y_final [n_cells][n_species] DEVICE or NULL: the replayed y(t_end)
  *   dL_dy0 [n_cells][n_species] DEVICE, written
  *   g_cells [n_cells][n_reactions] DEVICE or NULL: per-cell dL/dlog alpha
- *   dL_dlogalpha [n_reactions] DEVICE or NULL: sum of g_cells over cells in
- *     cell order (bitwise reproducible); needs g_cells
+ *   dL_dlogalpha [n_reactions] DEVICE or NULL: the sum over cells in cell
+ *     order (bitwise reproducible), from g_cells when given, else from the
+ *     workspace's rows max_cells cells at a time (same bits)
  *   cell_status [n_cells] DEVICE or NULL: AC_CELL_OK, AC_CELL_BADINPUT
  *     (dL_dy0 = lambda, no parameter terms) or AC_CELL_TAPE (tape_len < 0,
  *     > tape_cap, or an order outside 1..5; dL_dy0 = lambda).
  *   cell_stats [n_cells][AC_NSTAT] DEVICE or NULL: steps reversed, Newton
  *     iterations of the replays, Jacobians, factorisations and RHS
  *     evaluations (the rejection and order fields are 0).
- * Only rtol, atol and adj_recompute of opts are used (the tolerances scale
- * the replay's convergence test). With adj_recompute = 0 the forward replay
- * keeps the converged state of every step when tape_cap n_species 8 bytes
- * per slot come to at most 8 GiB in all, and the reverse sweep reads them
- * instead of recomputing each segment; the recomputed states are bitwise
- * the same, so only the time and the replay counters in cell_stats change.
- * The workspace grows its checkpoint store on the first call with a larger
- * tape_cap or the other state mode (a device allocation, after
- * synchronising the stream); about 64 tape_cap n_species bytes per slot,
- * plus 8 tape_cap n_species when every state is kept. Errors: AC_EINVAL for bad
- * sizes or NULL required arrays, AC_ENOMEM/AC_EHIP for allocation or
- * launch failures. */
+ * Only rtol, atol, adj_recompute and checkpoint_every of opts are used (the
+ * tolerances scale the replay's convergence test). Nothing is allocated:
+ * the workspace must hold an adjoint reservation (ac_ws_reserve_adjoint)
+ * with max_tape >= tape_cap and the same checkpoint interval, and gradient
+ * rows when dL_dlogalpha is asked for without g_cells; otherwise
+ * AC_ECAPACITY. Errors: AC_EINVAL for bad sizes or NULL required arrays,
+ * AC_EHIP for launch failures. */
 ac_status ac_integrate_adjoint(ac_ws *ws, const double *log_alpha, int64_t n_cells,
                                const double *y0, const double *T, const ac_integ_opts *opts,
                                const ac_event *tape, int32_t tape_cap, const int32_t *tape_len,

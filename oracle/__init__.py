@@ -38,7 +38,7 @@ class _Net(C.Structure):
     _fields_ = [("n_species", C.c_int), ("n_reactions", C.c_int),
                 ("reactants", C.c_void_p), ("products", C.c_void_p),
                 ("alpha", C.c_void_p), ("beta", C.c_void_p), ("gamma", C.c_void_p),
-                ("law", C.c_void_p), ("n_cond", C.c_int)]
+                ("law", C.c_void_p), ("n_cond", C.c_int), ("heat", C.c_void_p)]
 
 
 # Rate laws (oracle.h) and the per-cell conditions they read: (T, A_V,
@@ -49,11 +49,11 @@ NCOND = 4
 
 class _Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h0", C.c_double),
-                ("q_max", C.c_int), ("max_steps", C.c_int)]
+                ("q_max", C.c_int), ("max_steps", C.c_int), ("newton_tol", C.c_double)]
 
 
 EVENT_DTYPE = np.dtype([("type", np.int32), ("q", np.int32), ("val", np.float64)])
-OK, MAXSTEPS, HMIN, BADINPUT = 0, 1, 2, 3
+OK, MAXSTEPS, HMIN, BADINPUT, NEWTON_FAIL, SINGULAR, NONFINITE = 0, 1, 2, 3, 5, 6, 7
 EV_INIT, EV_RESCALE, EV_STEP = 1, 2, 3
 STAT_NAMES = ("steps", "reject_err", "reject_newton", "newton_it", "jac", "lu", "rhs", "q_last")
 
@@ -75,6 +75,8 @@ def lib():
         L.orc_rhs.argtypes = [vp, l, vp, vp, vp, vp]
         L.orc_rhs_k.argtypes = [vp, l, vp, vp, vp, vp]
         L.orc_jac_dense.argtypes = [vp, l, vp, vp, vp, vp]
+        L.orc_jac_pattern.argtypes = [vp, l, vp, vp, vp, vp, vp]
+        L.orc_jac_pattern.restype = i
         L.orc_vjp.argtypes = [vp, l, vp, vp, vp, vp, vp]
         L.orc_lu_factor.argtypes = [i, vp, vp]
         L.orc_lu_factor.restype = i
@@ -82,6 +84,9 @@ def lib():
         L.orc_lu_solve_t.argtypes = [i, vp, vp, vp]
         L.orc_bdf.argtypes = [vp, vp, l, vp, vp, d, vp, vp, vp, i, vp]
         L.orc_bdf_replay.argtypes = [vp, vp, l, vp, vp, vp, i, vp, i, vp, vp, vp, vp]
+        L.orc_rhs_thermal.argtypes = [vp, l, vp, vp, vp, vp, vp]
+        L.orc_jac_thermal.argtypes = [vp, l, vp, vp, vp, vp]
+        L.orc_bdf_thermal.argtypes = [vp, vp, l, vp, vp, vp, d, vp, vp]
         _lib = L
     return _lib
 
@@ -118,8 +123,11 @@ class NetView:
         law = getattr(net, "law", None)
         self.law = None if law is None else np.ascontiguousarray(law, np.int8)
         self.n_cond = NCOND if self.law is not None else 1
+        heat = getattr(net, "heat", None)
+        self.heat = None if heat is None else _f64(heat)
         self.s = _Net(self.ns, self.nr, _p(self.reactants), _p(self.products),
-                      _p(self.alpha), _p(self.beta), _p(self.gamma), _p(self.law), self.n_cond)
+                      _p(self.alpha), _p(self.beta), _p(self.gamma), _p(self.law), self.n_cond,
+                      _p(self.heat))
 
     @property
     def ptr(self):
@@ -201,6 +209,20 @@ def jac_dense(net, y, T, with_abs: bool = False):
     return (J, ab) if with_abs else J
 
 
+def jac_pattern(net, y, T, row_ptr, col):
+    """Jacobian values [cells, nnz] on a CSR pattern, as S dR/dn with the net
+    stoichiometry (jac_dense adds gross terms; equal up to rounding)."""
+    v = _view(net)
+    y = _cells(y, v.ns)
+    T = _cond(v, T)
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    cl = np.ascontiguousarray(col, np.int32)
+    jv = np.zeros((y.shape[0], int(rp[-1])))
+    if lib().orc_jac_pattern(v.ptr, y.shape[0], _p(y), _p(T), _p(rp), _p(cl), _p(jv)):
+        raise ValueError("a Jacobian term falls outside the pattern")
+    return jv
+
+
 def vjp(net, y, T, vec):
     v = _view(net)
     y = _cells(y, v.ns)
@@ -229,12 +251,13 @@ def lu_solve(LU, piv, b, trans: bool = False):
     return b
 
 
-def _opts(rtol, atol, h0, q_max, max_steps):
-    return _Opts(float(rtol), float(atol), float(h0), int(q_max), int(max_steps))
+def _opts(rtol, atol, h0, q_max, max_steps, newton_tol=0.0):
+    return _Opts(float(rtol), float(atol), float(h0), int(q_max), int(max_steps),
+                 float(newton_tol))
 
 
 def bdf(net, y0, T, t_end, rtol=1e-6, atol=1e-20, q_max=5, max_steps=100000, h0=0.0,
-        tape_cap: int = 0):
+        tape_cap: int = 0, newton_tol: float = 0.0):
     """Integrate every cell to t_end. Returns dict with y, status, stats and,
     if tape_cap > 0, the recorded step sequence (tape, tape_len)."""
     v = _view(net)
@@ -245,7 +268,7 @@ def bdf(net, y0, T, t_end, rtol=1e-6, atol=1e-20, q_max=5, max_steps=100000, h0=
     stats = np.zeros((n, len(STAT_NAMES)), np.int32)
     tape = np.zeros((n, max(tape_cap, 1)), EVENT_DTYPE) if tape_cap > 0 else None
     tlen = np.zeros(n, np.int32)
-    o = _opts(rtol, atol, h0, q_max, max_steps)
+    o = _opts(rtol, atol, h0, q_max, max_steps, newton_tol)
     lib().orc_bdf(v.ptr, C.byref(o), n, _p(y), _p(T), float(t_end), _p(status), _p(stats),
                   _p(tape), int(tape_cap), _p(tlen))
     out = dict(y=y, status=status, stats=stats)
@@ -278,3 +301,53 @@ def bdf_replay(net, y0, T, tape, tape_len, rtol=1e-6, atol=1e-20, dy0=None, dlog
     lib().orc_bdf_replay(v.ptr, C.byref(o), n, _p(y0), _p(T), _p(tape), tape.shape[1],
                          _p(tape_len), int(n_dir), _p(dy0), _p(dlogalpha), _p(y_out), _p(s_out))
     return y_out, s_out[:, :n_dir]
+
+
+# ------------------------------------------- temperature as a state
+
+def _therm(therm, n):
+    th = _f64(therm).reshape(-1, 3)
+    if th.shape[0] != n:
+        raise ValueError("therm needs (c_v, T_b, lambda) per cell")
+    return th
+
+
+def rhs_thermal(net, y, T, therm, with_abs: bool = False):
+    """d(n, T)/dt for states y [cells, ns+1] (last entry T); T: the
+    conditions array (its temperature column is not used); therm [cells, 3] =
+    (c_v, T_b, lambda)."""
+    v = _view(net)
+    y = _cells(y, v.ns + 1)
+    T = _cond(v, T)
+    th = _therm(therm, y.shape[0])
+    out = np.zeros_like(y)
+    ab = np.zeros_like(y) if with_abs else None
+    lib().orc_rhs_thermal(v.ptr, y.shape[0], _p(y), _p(T), _p(th), _p(out), _p(ab))
+    return (out, ab) if with_abs else out
+
+
+def jac_thermal(net, y, T, therm):
+    """Dense (ns+1) x (ns+1) Jacobian of the temperature-coupled system."""
+    v = _view(net)
+    y = _cells(y, v.ns + 1)
+    T = _cond(v, T)
+    th = _therm(therm, y.shape[0])
+    J = np.zeros((y.shape[0], v.ns + 1, v.ns + 1))
+    lib().orc_jac_thermal(v.ptr, y.shape[0], _p(y), _p(T), _p(th), _p(J))
+    return J
+
+
+def bdf_thermal(net, y0, T, therm, t_end, rtol=1e-6, atol=1e-20, q_max=5, max_steps=100000,
+                h0=0.0):
+    """Integrate the temperature-coupled system of every cell to t_end."""
+    v = _view(net)
+    y = np.array(_cells(y0, v.ns + 1), copy=True)
+    T = _cond(v, T)
+    th = _therm(therm, y.shape[0])
+    n = y.shape[0]
+    status = np.zeros(n, np.int32)
+    stats = np.zeros((n, len(STAT_NAMES)), np.int32)
+    o = _opts(rtol, atol, h0, q_max, max_steps)
+    lib().orc_bdf_thermal(v.ptr, C.byref(o), n, _p(y), _p(T), _p(th), float(t_end), _p(status),
+                          _p(stats))
+    return dict(y=y, status=status, stats=stats)

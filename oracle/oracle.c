@@ -223,6 +223,225 @@ void orc_jac_dense(const orc_net *net, long n_cells, const double *y, const doub
   }
 }
 
+/* The Jacobian on a given sparsity pattern (CSR: row_ptr[ns+1], col[nnz],
+ * columns ascending within a row), as the matrix product of eq.
+ * (matrix-form) differentiated: J = S dR/dn with the net stoichiometry, so
+ * a catalyst (in and out of the same reaction) adds nothing to its own row.
+ * Reaction by reaction, every reactant slot's derivative times each net
+ * entry of the reaction's column of S goes to its entry. A term outside the
+ * pattern is an error (returns 1). */
+static int pattern_index(const int *row_ptr, const int *col, int i, int a) {
+  int lo = row_ptr[i], hi = row_ptr[i + 1];
+  while (lo < hi) {
+    int mid = (lo + hi) / 2;
+    if (col[mid] < a) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < row_ptr[i + 1] && col[lo] == a) ? lo : -1;
+}
+
+/* Net column of S for reaction j: species and coefficients, zeros dropped. */
+static int net_column(const orc_net *net, int j, int *sp, int *coef) {
+  int m = 0;
+  for (int t = 0; t < NRS + NPS; ++t) {
+    int x = t < NRS ? net->reactants[j * NRS + t] : net->products[j * NPS + t - NRS];
+    if (x < 0) continue;
+    int q = 0;
+    while (q < m && sp[q] != x) ++q;
+    if (q == m) {
+      sp[m] = x;
+      coef[m] = 0;
+      ++m;
+    }
+    coef[q] += t < NRS ? -1 : 1;
+  }
+  return m;
+}
+
+/* One term of the pattern Jacobian: reaction j's derivative in reactant
+ * slot s, times coef, goes to entry e. */
+typedef struct {
+  int j, s, e, coef;
+} pat_term;
+
+/* The terms of S dR/dn on the pattern, reaction by reaction (the order in
+ * which every entry receives them); NULL with *bad = 1 if a term falls
+ * outside the pattern. */
+static pat_term *pattern_terms(const orc_net *net, const int *row_ptr, const int *col, int *nt,
+                               int *bad) {
+  const int nr = net->n_reactions;
+  pat_term *t = xcalloc((size_t)nr * NRS * (NRS + NPS), sizeof(pat_term));
+  int m = 0;
+  *bad = 0;
+  for (int j = 0; j < nr; ++j) {
+    int sp[NRS + NPS], coef[NRS + NPS];
+    const int nc = net_column(net, j, sp, coef);
+    for (int s = 0; s < NRS; ++s) {
+      int a = net->reactants[j * NRS + s];
+      if (a < 0) continue;
+      for (int q = 0; q < nc; ++q) {
+        if (coef[q] == 0) continue;
+        int e = pattern_index(row_ptr, col, sp[q], a);
+        if (e < 0) {
+          *bad = 1;
+          free(t);
+          return NULL;
+        }
+        t[m].j = j;
+        t[m].s = s;
+        t[m].e = e;
+        t[m].coef = coef[q];
+        ++m;
+      }
+    }
+  }
+  *nt = m;
+  return t;
+}
+
+int orc_jac_pattern(const orc_net *net, long n_cells, const double *y, const double *T,
+                    const int *row_ptr, const int *col, double *jvals) {
+  const int ns = net->n_species, nr = net->n_reactions;
+  const size_t nnz = (size_t)row_ptr[ns];
+  int nt = 0, bad = 0;
+  pat_term *t = pattern_terms(net, row_ptr, col, &nt, &bad);
+  if (bad) return 1;
+#pragma omp parallel num_threads(g_threads)
+  {
+    double *k = xcalloc((size_t)nr, sizeof(double));
+#pragma omp for schedule(static)
+    for (long c = 0; c < n_cells; ++c) {
+      const double *yc = y + (size_t)c * ns;
+      double *jv = jvals + (size_t)c * nnz;
+      cell_rate_coeffs(net, T + (size_t)c * n_cond(net), k);
+      memset(jv, 0, sizeof(double) * nnz);
+      for (int q = 0; q < nt; ++q)
+        jv[t[q].e] += t[q].coef * rate_slot_derivative(net, k, yc, t[q].j, t[q].s);
+    }
+    free(k);
+  }
+  free(t);
+  return 0;
+}
+
+/* ------------------------------------------- temperature as a state
+ *
+ * Codes that solve temperature and abundances together in the stiff
+ * solver (Sec. 5) add T to the state. Here the gas heats by the energy the
+ * reactions release and relaxes towards a background temperature:
+ *   dT/dt = (sum_j heat_j R_j) / c_v - lambda (T - T_b),
+ * heat_j [erg] per reaction event, per-cell c_v [erg cm^-3 K^-1], T_b [K]
+ * and lambda [1/s] (therm[c] = (c_v, T_b, lambda)). The coefficients follow
+ * the state's T, so the Jacobian gains a T column through dk/dT and a T
+ * row through the heating term. */
+
+/* d ln k_j / dT at the cell's conditions (rate laws of rate_coeff). */
+static double rate_dlog_dT(const orc_net *net, int j, double T) {
+  const int law = net->law ? net->law[j] : ORC_LAW_KOOIJ;
+  switch (law) {
+    case ORC_LAW_CRP:
+    case ORC_LAW_PHOTO:
+      return 0.0;
+    case ORC_LAW_CRPHOT:
+      return net->beta[j] / T;
+    default:
+      return (net->beta[j] + net->gamma[j] / T) / T;
+  }
+}
+
+/* Conditions with the state's temperature in place of cond[0]. */
+static void cond_at(const orc_net *net, const double *cond, double T, double *out) {
+  for (int i = 0; i < n_cond(net); ++i) out[i] = cond[i];
+  out[0] = T;
+}
+
+static void cell_rhs_thermal(const orc_net *net, const double *cond, const double *therm,
+                             const double *y, double *k, double *f, double *absterm) {
+  const int ns = net->n_species, nr = net->n_reactions;
+  double c[ORC_NCOND];
+  cond_at(net, cond, y[ns], c);
+  cell_rate_coeffs(net, c, k);
+  cell_rhs_k(net, k, y, f, absterm);
+  double q = 0.0, qa = 0.0;
+  if (net->heat)
+    for (int j = 0; j < nr; ++j) {
+      double h = net->heat[j] * reaction_rate(net, k, y, j);
+      q += h;
+      qa += fabs(h);
+    }
+  f[ns] = q / therm[0] - therm[2] * (y[ns] - therm[1]);
+  if (absterm) absterm[ns] = qa / therm[0] + fabs(therm[2] * (y[ns] - therm[1]));
+}
+
+/* Dense (ns+1) x (ns+1) Jacobian of the coupled system, row-major. */
+static void cell_jac_thermal(const orc_net *net, const double *cond, const double *therm,
+                             const double *y, double *k, double *Jn, double *Jb) {
+  const int ns = net->n_species, nr = net->n_reactions, n = ns + 1;
+  const double T = y[ns];
+  double c[ORC_NCOND];
+  cond_at(net, cond, T, c);
+  cell_rate_coeffs(net, c, k);
+  cell_jac(net, k, y, Jb, NULL);
+  for (int i = 0; i < ns; ++i) {
+    for (int a = 0; a < ns; ++a) Jn[(size_t)i * n + a] = Jb[(size_t)i * ns + a];
+    Jn[(size_t)i * n + ns] = 0.0;
+  }
+  for (int a = 0; a <= ns; ++a) Jn[(size_t)ns * n + a] = 0.0;
+  /* T column: d(dn_i/dt)/dT = sum_j S_ij R_j dln k_j/dT, same bookkeeping */
+  for (int j = 0; j < nr; ++j) {
+    const double dr = reaction_rate(net, k, y, j) * rate_dlog_dT(net, j, T);
+    for (int s = 0; s < NRS; ++s) {
+      int a = net->reactants[j * NRS + s];
+      if (a >= 0) Jn[(size_t)a * n + ns] -= dr;
+    }
+    for (int s = 0; s < NPS; ++s) {
+      int p = net->products[j * NPS + s];
+      if (p >= 0) Jn[(size_t)p * n + ns] += dr;
+    }
+    if (net->heat) {
+      /* T row: heating through every reactant density, and through T */
+      const double hj = net->heat[j] / therm[0];
+      for (int s = 0; s < NRS; ++s) {
+        int a = net->reactants[j * NRS + s];
+        if (a >= 0) Jn[(size_t)ns * n + a] += hj * rate_slot_derivative(net, k, y, j, s);
+      }
+      Jn[(size_t)ns * n + ns] += hj * dr;
+    }
+  }
+  Jn[(size_t)ns * n + ns] -= therm[2];
+}
+
+void orc_rhs_thermal(const orc_net *net, long n_cells, const double *y, const double *cond,
+                     const double *therm, double *dydt, double *absterm) {
+  const int n = net->n_species + 1, nr = net->n_reactions;
+#pragma omp parallel num_threads(g_threads)
+  {
+    double *k = xcalloc((size_t)nr, sizeof(double));
+#pragma omp for schedule(static)
+    for (long c = 0; c < n_cells; ++c)
+      cell_rhs_thermal(net, cond + (size_t)c * n_cond(net), therm + (size_t)c * 3,
+                       y + (size_t)c * n, k, dydt + (size_t)c * n,
+                       absterm ? absterm + (size_t)c * n : NULL);
+    free(k);
+  }
+}
+
+void orc_jac_thermal(const orc_net *net, long n_cells, const double *y, const double *cond,
+                     const double *therm, double *J) {
+  const int ns = net->n_species, n = ns + 1, nr = net->n_reactions;
+#pragma omp parallel num_threads(g_threads)
+  {
+    double *k = xcalloc((size_t)nr, sizeof(double));
+    double *Jb = xcalloc((size_t)ns * ns, sizeof(double));
+#pragma omp for schedule(static)
+    for (long c = 0; c < n_cells; ++c)
+      cell_jac_thermal(net, cond + (size_t)c * n_cond(net), therm + (size_t)c * 3,
+                       y + (size_t)c * n, k, J + (size_t)c * n * n, Jb);
+    free(k);
+    free(Jb);
+  }
+}
+
 /* ------------------------------------------------------------- VJP */
 
 /* (S^T v)_j: the net change of <v, n> per unit of reaction j. */
@@ -467,14 +686,28 @@ static double pow_neg(double x, double e) { /* x^(-e), with 0 -> inf */
 
 typedef struct {
   const orc_net *net;
-  const double *k;
+  double *k;
   int n;
   int *st;
+  const double *cond;    /* temperature-coupled mode: the cell's conditions, */
+  const double *therm;   /* (c_v, T_b, lambda), or NULL for T held fixed */
+  double *Jb;            /* ns x ns scratch of the coupled Jacobian */
 } cell_ctx;
 
 static void F(cell_ctx *cx, const double *y, double *f) {
-  cell_rhs_k(cx->net, cx->k, y, f, NULL);
+  if (cx->therm)
+    cell_rhs_thermal(cx->net, cx->cond, cx->therm, y, cx->k, f, NULL);
+  else
+    cell_rhs_k(cx->net, cx->k, y, f, NULL);
   if (cx->st) cx->st[ORC_ST_RHS]++;
+}
+
+/* The Jacobian of F, n x n. */
+static void JF(cell_ctx *cx, const double *y, double *J) {
+  if (cx->therm)
+    cell_jac_thermal(cx->net, cx->cond, cx->therm, y, cx->k, J, cx->Jb);
+  else
+    cell_jac(cx->net, cx->k, y, J, NULL);
 }
 
 static void build_newton_matrix(int n, double c, const double *J, double *M) {
@@ -486,16 +719,20 @@ static void build_newton_matrix(int n, double c, const double *J, double *M) {
  * returns 1 if converged. */
 static int newton(cell_ctx *cx, const double *ypred, double c, double cM, const double *psi,
                   const double *LU, const int *piv, const double *scale, double tol, double *ynew,
-                  double *d, double *f, double *dy, int *n_iter) {
+                  double *d, double *f, double *dy, int *n_iter, int *nonfinite) {
   const double corr = (c == cM) ? 1.0 : 2.0 / (1.0 + c / cM);
   const int n = cx->n;
   memcpy(ynew, ypred, sizeof(double) * n);
   for (int i = 0; i < n; ++i) d[i] = 0.0;
   double prev = 0.0;
   int conv = 0, it;
+  *nonfinite = 0;
   for (it = 0; it < NEWTON_MAXITER; ++it) {
     F(cx, ynew, f);
-    if (!all_finite(n, f)) break;
+    if (!all_finite(n, f)) {
+      *nonfinite = 1;
+      break;
+    }
     for (int i = 0; i < n; ++i) dy[i] = c * f[i] - psi[i] - d[i];
     orc_lu_solve(n, LU, piv, dy);
     if (corr != 1.0)
@@ -577,15 +814,19 @@ static int valid_input(int n, const double *y, const double *cond, int nc) {
 }
 
 static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, const double *cond,
-                    double t_end, int *st, tape_w *tw) {
-  const int n = net->n_species, nr = net->n_reactions;
-  if (!valid_input(n, y, cond, n_cond(net))) return ORC_BADINPUT;
+                    const double *therm, double t_end, int *st, tape_w *tw) {
+  const int ns = net->n_species, nr = net->n_reactions, n = ns + (therm ? 1 : 0);
+  if (!valid_input(ns, y, cond, n_cond(net))) return ORC_BADINPUT;
+  if (therm && !(isfinite(y[ns]) && y[ns] > 0.0 && therm[0] > 0.0 && isfinite(therm[0]) &&
+                 therm[1] > 0.0 && isfinite(therm[1]) && therm[2] >= 0.0 && isfinite(therm[2])))
+    return ORC_BADINPUT;
   if (!(t_end > 0.0)) return ORC_OK;
   bdf_consts K;
   bdf_constants(&K);
   const int qmax = o->q_max;
   const double rtol = o->rtol, atol = o->atol;
-  const double tol = fmax(10.0 * DBL_EPSILON / rtol, fmin(0.03, sqrt(rtol)));
+  const double tol = o->newton_tol > 0.0 ? o->newton_tol
+                                         : fmax(10.0 * DBL_EPSILON / rtol, fmin(0.03, sqrt(rtol)));
 
   double *k = xcalloc((size_t)nr, sizeof(double));
   double *D = xcalloc((size_t)NDROW * n, sizeof(double));
@@ -599,9 +840,10 @@ static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, const 
   double *d = xcalloc((size_t)n, sizeof(double));
   double *f = xcalloc((size_t)n, sizeof(double));
   double *dy = xcalloc((size_t)n, sizeof(double));
+  double *Jb = therm ? xcalloc((size_t)ns * ns, sizeof(double)) : NULL;
 
-  cell_rate_coeffs(net, cond, k);
-  cell_ctx cx = {net, k, n, st};
+  if (!therm) cell_rate_coeffs(net, cond, k);
+  cell_ctx cx = {net, k, n, st, cond, therm, Jb};
   F(&cx, y, f);
   double h = o->h0 > 0.0 ? fmin(o->h0, t_end) : initial_step(&cx, y, f, rtol, atol, t_end);
   tape_put(tw, ORC_EV_INIT, 1, h);
@@ -609,10 +851,14 @@ static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, const 
     D[x] = y[x];
     D[n + x] = h * f[x];
   }
-  cell_jac(net, k, y, J, NULL);
+  JF(&cx, y, J);
   if (st) st[ORC_ST_JAC]++;
 
   int status = ORC_OK, q = 1, n_equal = 0, lu_valid = 0, steps = 0;
+  /* why the last attempt was rejected, reported if h falls below h_min:
+   * the error test, a Newton failure with finite values, a non-finite RHS,
+   * or an exactly singular Newton matrix */
+  int last_fail = ORC_HMIN, lu_info = 0;
   double cM = 0.0;
   double t = 0.0, h_abs = h;
   while (t < t_end) {
@@ -621,11 +867,11 @@ static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, const 
       break;
     }
     const double hmin = 10.0 * (nextafter(t, INFINITY) - t);
-    int jac_fresh = 0, n_iter = 0;
+    int jac_fresh = 0, n_iter = 0, nonfin = 0;
     double t_new = t, en = 0.0, safety = 0.0;
     for (;;) { /* attempts */
       if (h_abs < hmin) {
-        status = ORC_HMIN;
+        status = last_fail;
         goto done;
       }
       t_new = t + h_abs;
@@ -652,19 +898,21 @@ static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, const 
       for (;;) {
         if (!lu_valid || fabs(c / cM - 1.0) > 0.3) {
           build_newton_matrix(n, c, J, LU);
-          orc_lu_factor(n, LU, piv);
+          lu_info = orc_lu_factor(n, LU, piv);
           if (st) st[ORC_ST_LU]++;
           lu_valid = 1;
           cM = c;
         }
-        conv = newton(&cx, ypred, c, cM, psi, LU, piv, scale, tol, ynew, d, f, dy, &n_iter);
+        conv = newton(&cx, ypred, c, cM, psi, LU, piv, scale, tol, ynew, d, f, dy, &n_iter,
+                      &nonfin);
         if (conv || jac_fresh) break;
-        cell_jac(net, k, ypred, J, NULL);
+        JF(&cx, ypred, J);
         if (st) st[ORC_ST_JAC]++;
         jac_fresh = 1;
         lu_valid = 0;
       }
       if (!conv) {
+        last_fail = lu_info ? ORC_SINGULAR : nonfin ? ORC_NONFINITE : ORC_NEWTON_FAIL;
         h_abs *= 0.5;
         rescale_diffs(n, q, 0.5, D);
         tape_put(tw, ORC_EV_RESCALE, q, 0.5);
@@ -676,6 +924,7 @@ static int bdf_cell(const orc_net *net, const orc_bdf_opts *o, double *y, const 
       for (int x = 0; x < n; ++x) scale[x] = atol + rtol * fabs(ynew[x]);
       en = rms_scaled(n, d, K.errc[q], scale);
       if (en > 1.0) {
+        last_fail = ORC_HMIN;
         double factor = fmax(MIN_FACTOR, safety * pow_neg(en, 1.0 / (q + 1)));
         h_abs *= factor;
         rescale_diffs(n, q, factor, D);
@@ -713,7 +962,7 @@ done:
     st[ORC_ST_QLAST] = q;
   }
   free(k); free(D); free(J); free(LU); free(piv); free(ypred); free(psi);
-  free(scale); free(ynew); free(d); free(f); free(dy);
+  free(scale); free(ynew); free(d); free(f); free(dy); free(Jb);
   return status;
 }
 
@@ -726,9 +975,25 @@ void orc_bdf(const orc_net *net, const orc_bdf_opts *opt, long n_cells, double *
     int *st = stats ? stats + (size_t)c * ORC_NSTAT : NULL;
     if (st) memset(st, 0, sizeof(int) * ORC_NSTAT);
     tape_w tw = {tape ? tape + (size_t)c * tape_cap : NULL, tape_cap, 0, 0};
-    int s = bdf_cell(net, opt, y + (size_t)c * ns, T + (size_t)c * n_cond(net), t_end, st, &tw);
+    int s = bdf_cell(net, opt, y + (size_t)c * ns, T + (size_t)c * n_cond(net), NULL, t_end, st,
+                     &tw);
     if (status) status[c] = s;
     if (tape_len) tape_len[c] = tw.overflow ? -1 : tw.len;
+  }
+}
+
+void orc_bdf_thermal(const orc_net *net, const orc_bdf_opts *opt, long n_cells, double *y,
+                     const double *cond, const double *therm, double t_end, int *status,
+                     int *stats) {
+  const int n = net->n_species + 1;
+#pragma omp parallel for num_threads(g_threads) schedule(dynamic, 1)
+  for (long c = 0; c < n_cells; ++c) {
+    int *st = stats ? stats + (size_t)c * ORC_NSTAT : NULL;
+    if (st) memset(st, 0, sizeof(int) * ORC_NSTAT);
+    tape_w tw = {NULL, 0, 0, 0};
+    int s = bdf_cell(net, opt, y + (size_t)c * n, cond + (size_t)c * n_cond(net),
+                     therm + (size_t)c * 3, t_end, st, &tw);
+    if (status) status[c] = s;
   }
 }
 
@@ -790,7 +1055,7 @@ static void replay_cell(const orc_net *net, const orc_bdf_opts *o, const double 
   double *sd = xcalloc((size_t)n, sizeof(double));
 
   cell_rate_coeffs(net, cond, k);
-  cell_ctx cx = {net, k, n, NULL};
+  cell_ctx cx = {net, k, n, NULL, cond, NULL, NULL};
   memcpy(D, y0, sizeof(double) * n);
   for (int r = 0; r < n_dir; ++r)
     for (int x = 0; x < n; ++x) sD[(size_t)r * NDROW * n + x] = dy0 ? dy0[(size_t)r * n + x] : 0.0;

@@ -27,6 +27,8 @@ typedef struct {
   const signed char *law; /* [n_reactions] ORC_LAW_*, or NULL: every reaction ORC_LAW_KOOIJ */
   int n_cond;             /* doubles of per-cell conditions: 1 (T) or ORC_NCOND (T, A_V,
                              zeta/zeta_0, G_0); 0 is taken as 1 */
+  const double *heat;     /* [n_reactions] energy released per reaction event [erg] for the
+                             temperature-coupled mode, or NULL (no chemical heating) */
 } orc_net;
 
 /* Rate laws (the coefficients depend on the temperature, the cosmic-ray
@@ -70,6 +72,14 @@ void orc_rhs_k(const orc_net *net, long n_cells, const double *k, const double *
 void orc_jac_dense(const orc_net *net, long n_cells, const double *y, const double *T,
                    double *J, double *absJ);
 
+/* The Jacobian's values on a given CSR pattern (row_ptr[n_species+1],
+ * col[nnz] ascending per row): jvals[c][e] = J_{row(e), col[e]} as
+ * S dR/dn with the net stoichiometry (orc_jac_dense uses the gross
+ * bookkeeping; the two agree up to rounding). Returns 1 if a nonzero term
+ * falls outside the pattern, else 0. */
+int orc_jac_pattern(const orc_net *net, long n_cells, const double *y, const double *T,
+                    const int *row_ptr, const int *col, double *jvals);
+
 /* Vector-Jacobian products for cotangent v[c][i]:
  *   gy[c][a]     = sum_i v_i J_ia                        (may be NULL)
  *   glog[c][j]   = sum_i v_i d(dydt_i)/d(log alpha_j) = r_j (S^T v)_j
@@ -86,7 +96,12 @@ void orc_lu_solve_t(int n, const double *LU, const int *piv, double *b);  /* A^T
 
 /* ---------------------------------------------------------------- BDF */
 
-enum { ORC_OK = 0, ORC_MAXSTEPS = 1, ORC_HMIN = 2, ORC_BADINPUT = 3 };
+/* Cell outcomes. When the step size falls below h_min the code names why
+ * the last attempt was rejected: the error test (HMIN), a Newton iteration
+ * that did not converge on finite values (NEWTON_FAIL), an exactly
+ * singular Newton matrix (SINGULAR) or a non-finite RHS (NONFINITE). */
+enum { ORC_OK = 0, ORC_MAXSTEPS = 1, ORC_HMIN = 2, ORC_BADINPUT = 3, ORC_NEWTON_FAIL = 5,
+       ORC_SINGULAR = 6, ORC_NONFINITE = 7 };
 enum { ORC_EV_INIT = 1, ORC_EV_RESCALE = 2, ORC_EV_STEP = 3 };
 
 typedef struct {
@@ -94,6 +109,7 @@ typedef struct {
   double h0;        /* first step; <= 0 selects it automatically */
   int q_max;        /* 1..5; 1 is adaptive backward Euler */
   int max_steps;
+  double newton_tol; /* corrector tolerance (weighted RMS); <= 0: max(10 eps/rtol, min(0.03, sqrt(rtol))) */
 } orc_bdf_opts;
 
 typedef struct {
@@ -114,6 +130,22 @@ enum { ORC_ST_STEPS = 0, ORC_ST_REJECT_ERR, ORC_ST_REJECT_NEWTON, ORC_ST_NEWTON_
 void orc_bdf(const orc_net *net, const orc_bdf_opts *opt, long n_cells, double *y,
              const double *T, double t_end, int *status, int *stats,
              orc_event *tape, int tape_cap, int *tape_len);
+
+/* Temperature as a state variable (codes that solve temperature and
+ * abundances together, Sec. 5): per cell the state is (n_1..n_ns, T),
+ * [n_cells][n_species + 1], the coefficients follow the state's T (cond[0]
+ * is ignored, the other conditions are used), and
+ *   dT/dt = (sum_j heat_j R_j) / c_v - lambda (T - T_b),
+ * therm[c] = (c_v [erg cm^-3 K^-1], T_b [K], lambda [1/s]).
+ * orc_jac_thermal writes the dense (ns+1) x (ns+1) Jacobian per cell;
+ * orc_bdf_thermal integrates the coupled system with the BDF above. */
+void orc_rhs_thermal(const orc_net *net, long n_cells, const double *y, const double *cond,
+                     const double *therm, double *dydt, double *absterm);
+void orc_jac_thermal(const orc_net *net, long n_cells, const double *y, const double *cond,
+                     const double *therm, double *J);
+void orc_bdf_thermal(const orc_net *net, const orc_bdf_opts *opt, long n_cells, double *y,
+                     const double *cond, const double *therm, double t_end, int *status,
+                     int *stats);
 
 /* Replays a recorded step sequence with the corrector solved to convergence
  * and propagates n_dir forward sensitivities. Direction d perturbs the

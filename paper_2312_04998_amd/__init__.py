@@ -22,6 +22,7 @@ AC_LAYOUT_CSR, AC_LAYOUT_SELL, AC_LAYOUT_COO, AC_LAYOUT_RUNS, AC_LAYOUT_CCS = 0,
 AC_ORDER_NATURAL, AC_ORDER_NNZ_DESC, AC_ORDER_RCM = 0, 1, 2
 AC_FMT_COO, AC_FMT_CCS, AC_FMT_CRS, AC_FMT_SELL = 0, 1, 2, 3
 AC_CELL_OK, AC_CELL_MAXSTEPS, AC_CELL_HMIN, AC_CELL_BADINPUT, AC_CELL_TAPE = 0, 1, 2, 3, 4
+AC_CELL_NEWTON_FAIL, AC_CELL_SINGULAR, AC_CELL_NONFINITE = 5, 6, 7
 LAYOUTS = {"csr": AC_LAYOUT_CSR, "sell": AC_LAYOUT_SELL, "coo": AC_LAYOUT_COO,
            "runs": AC_LAYOUT_RUNS, "ccs": AC_LAYOUT_CCS}
 ORDERINGS = {"natural": AC_ORDER_NATURAL, "nnz": AC_ORDER_NNZ_DESC, "rcm": AC_ORDER_RCM}
@@ -40,7 +41,7 @@ class NetDesc(C.Structure):
                 ("composition", C.c_void_p), ("n_elem", C.c_int32),
                 ("check_balance", C.c_int32), ("layout", C.c_int32), ("ordering", C.c_int32),
                 ("chunk", C.c_int32), ("sell_c", C.c_int32), ("sell_sigma", C.c_int32),
-                ("block", C.c_int32), ("rate_law", C.c_void_p)]
+                ("block", C.c_int32), ("rate_law", C.c_void_p), ("heat", C.c_void_p)]
 
 
 # Rate laws (ac_rate_law) and the per-cell conditions of a network that has
@@ -68,6 +69,8 @@ def _load() -> C.CDLL:
         "ac_jac": [vp, vp, i64, vp, vp, vp, vp],
         "ac_rhs_jac": [vp, vp, i64, vp, vp, vp, vp, vp],
         "ac_vjp": [vp, vp, i64, vp, vp, vp, vp, vp, vp],
+        "ac_rhs_thermal": [vp, vp, i64, vp, vp, vp, vp, vp],
+        "ac_jac_thermal": [vp, vp, i64, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -89,6 +92,9 @@ def _load() -> C.CDLL:
         "ac_integrate_adjoint": [vp, vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
                                  vp, vp],
         "ac_replay": [vp, vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp],
+        "ac_integrate_thermal": [vp, vp, i64, vp, vp, vp, d, vp, vp, vp, vp],
+        "ac_ws_reserve_adjoint": [vp, vp],
+        "ac_ws_adjoint_info": [vp, vp, vp, vp, vp],
     }
     for name, args in sig2.items():
         f = getattr(L, name)
@@ -141,7 +147,8 @@ def _check_dev(t, shape, name: str):
 
 class IntegOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h0", C.c_double),
-                ("q_max", C.c_int32), ("max_steps", C.c_int32), ("adj_recompute", C.c_int32)]
+                ("q_max", C.c_int32), ("max_steps", C.c_int32), ("adj_recompute", C.c_int32),
+                ("checkpoint_every", C.c_int32), ("newton_tol", C.c_double)]
 
 
 EVENT_DTYPE = np.dtype([("type", np.int32), ("q", np.int32), ("val", np.float64)])
@@ -156,7 +163,7 @@ class Network:
     def __init__(self, reactants, products, alpha, beta, gamma, composition=None,
                  layout: str = "sell", ordering: str = "nnz", chunk: int = 0, sell_c: int = 0,
                  sell_sigma: int = 0, check_balance: bool = False, block: int = 0,
-                 rate_law=None):
+                 rate_law=None, heat=None):
         self._rea = np.ascontiguousarray(reactants, np.int32)
         self._pro = np.ascontiguousarray(products, np.int32)
         self._a = np.ascontiguousarray(alpha, np.float64)
@@ -165,6 +172,7 @@ class Network:
         self._comp = None if composition is None else np.ascontiguousarray(composition, np.int8)
         self._law = None if rate_law is None else np.ascontiguousarray(rate_law, np.int8)
         self.n_cond = 1 if self._law is None else AC_NCOND
+        self._heat = None if heat is None else np.ascontiguousarray(heat, np.float64)
         self.n_reactions = int(self._rea.shape[0])
         if composition is not None:
             self.n_species = int(self._comp.shape[0])
@@ -175,7 +183,7 @@ class Network:
                     _ptr(self._a), _ptr(self._b), _ptr(self._g), _ptr(self._comp),
                     0 if self._comp is None else self._comp.shape[1], int(check_balance),
                     LAYOUTS[layout], ORDERINGS[ordering], chunk, sell_c, sell_sigma, block,
-                    _ptr(self._law))
+                    _ptr(self._law), _ptr(self._heat))
         h = C.c_void_p()
         check(lib.ac_net_create(C.byref(d), C.byref(h)), "ac_net_create")
         self.handle = h
@@ -188,7 +196,8 @@ class Network:
     @classmethod
     def from_synth(cls, net, **kw):
         return cls(net.reactants, net.products, net.alpha, net.beta, net.gamma,
-                   composition=net.composition, rate_law=getattr(net, "law", None), **kw)
+                   composition=net.composition, rate_law=getattr(net, "law", None),
+                   heat=getattr(net, "heat", None), **kw)
 
     def cond_shape(self, n: int):
         """Shape of the per-cell conditions array T for n cells."""
@@ -325,6 +334,35 @@ def ac_vjp(net: Network, log_alpha, y, T, v, gy, g_logalpha, stream=None):
                      _ptr(g_logalpha), _stream(stream)), "ac_vjp")
 
 
+def _thermal_args(net: Network, y, T, therm):
+    n = T.shape[0]
+    _check_dev(T, net.cond_shape(n), "T")
+    _check_dev(y, (n, net.n_species + 1), "y")
+    _check_dev(therm, (n, 3), "therm")
+    return n
+
+
+def ac_rhs_thermal(net: Network, log_alpha, y, T, therm, dydt, stream=None):
+    """Temperature as a state: y, dydt [n, ns+1] (last entry T), therm [n, 3]
+    = (c_v, T_b, lambda)."""
+    n = _thermal_args(net, y, T, therm)
+    _check_dev(dydt, (n, net.n_species + 1), "dydt")
+    if log_alpha is not None:
+        _check_dev(log_alpha, (net.n_reactions,), "log_alpha")
+    check(lib.ac_rhs_thermal(net.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T), _ptr(therm),
+                             _ptr(dydt), _stream(stream)), "ac_rhs_thermal")
+
+
+def ac_jac_thermal(net: Network, log_alpha, y, T, therm, jvals, stream=None):
+    """jvals [n, nnz_j + 2 ns + 1]: pattern values, T column, T row, corner."""
+    n = _thermal_args(net, y, T, therm)
+    _check_dev(jvals, (n, net.nnz_j + 2 * net.n_species + 1), "jvals")
+    if log_alpha is not None:
+        _check_dev(log_alpha, (net.n_reactions,), "log_alpha")
+    check(lib.ac_jac_thermal(net.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T), _ptr(therm),
+                             _ptr(jvals), _stream(stream)), "ac_jac_thermal")
+
+
 def ac_sparse_format(dense, fmt: int, width: int = 0):
     """Host storage builder (Sec. 2.2 formats) for a small integer matrix."""
     A = np.ascontiguousarray(dense, np.int32)
@@ -358,10 +396,20 @@ def ac_lu_solve(LU, piv, b, trans=False, stream=None):
 
 # -------------------------------------------------------------- integrator
 
-class Workspace:
-    """Owns an ac_ws (integrator slots) for one network."""
+class AdjReserve(C.Structure):
+    _fields_ = [("max_tape", C.c_int32), ("checkpoint_every", C.c_int32),
+                ("keep_states", C.c_int32), ("max_cells", C.c_int32)]
 
-    def __init__(self, net: Network, n_slots: int = 0):
+
+class Workspace:
+    """Owns an ac_ws (integrator slots) for one network. With adj_max_tape >
+    0 it also reserves room for the adjoint and the replay at creation
+    (ac_ws_reserve_adjoint); adjoint() and replay() reserve (explicitly, in
+    a separate call before theirs) when a tape is longer than what was
+    reserved, so the library call itself never allocates."""
+
+    def __init__(self, net: Network, n_slots: int = 0, adj_max_tape: int = 0,
+                 checkpoint_every: int = 0, keep_states: bool = True, adj_max_cells: int = 0):
         self.net = net
         h = C.c_void_p()
         check(lib.ac_ws_create(net.handle, int(n_slots), C.byref(h)), "ac_ws_create")
@@ -369,6 +417,28 @@ class Workspace:
         ns, nb = C.c_int32(), C.c_int64()
         check(lib.ac_ws_info(h, C.byref(ns), C.byref(nb)), "ac_ws_info")
         self.n_slots, self.bytes = ns.value, nb.value
+        self.keep_states, self.adj_max_cells = bool(keep_states), int(adj_max_cells)
+        self.adj_max_tape, self.checkpoint_every = 0, int(checkpoint_every) or 64
+        if adj_max_tape > 0:
+            self.reserve_adjoint(adj_max_tape, checkpoint_every, keep_states, adj_max_cells)
+
+    def reserve_adjoint(self, max_tape: int, checkpoint_every: int = 0, keep_states: bool = True,
+                        max_cells: int = 0):
+        """ac_ws_reserve_adjoint: room for tapes of up to max_tape events."""
+        r = AdjReserve(int(max_tape), int(checkpoint_every), int(bool(keep_states)), int(max_cells))
+        check(lib.ac_ws_reserve_adjoint(self.handle, C.byref(r)), "ac_ws_reserve_adjoint")
+        mt, ce, ks, mc = (C.c_int32() for _ in range(4))
+        check(lib.ac_ws_adjoint_info(self.handle, C.byref(mt), C.byref(ce), C.byref(ks),
+                                     C.byref(mc)), "ac_ws_adjoint_info")
+        self.adj_max_tape, self.checkpoint_every = mt.value, ce.value
+        self.keeps_states, self.adj_max_cells = bool(ks.value), mc.value
+        self.keep_states = bool(keep_states)
+
+    def _ensure_adjoint(self, tape_cap: int, checkpoint_every: int):
+        every = int(checkpoint_every) or 64
+        if tape_cap > self.adj_max_tape or every != self.checkpoint_every:
+            self.reserve_adjoint(max(tape_cap, self.adj_max_tape if every == self.checkpoint_every
+                                     else 0), every, self.keep_states, self.adj_max_cells)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -382,7 +452,7 @@ class Workspace:
             pass
 
     def integrate(self, y, T, t_end, rtol=1e-6, atol=1e-20, q_max=5, max_steps=100000, h0=0.0,
-                  log_alpha=None, tape_cap=0, plain=False, stream=None):
+                  log_alpha=None, tape_cap=0, plain=False, newton_tol=0.0, stream=None):
         """Integrates y (device, in place) to t_end. Returns dict of device
         tensors: status [n], stats [n, NSTAT] and, with tape_cap > 0, the
         recorded steps (tape [n, tape_cap] of EVENT_DTYPE bytes, tape_len)."""
@@ -395,7 +465,8 @@ class Workspace:
         dev = y.device
         status = torch.empty(n, dtype=torch.int32, device=dev)
         stats = torch.empty((n, NSTAT), dtype=torch.int32, device=dev)
-        o = IntegOpts(float(rtol), float(atol), float(h0), int(q_max), int(max_steps), 0)
+        o = IntegOpts(float(rtol), float(atol), float(h0), int(q_max), int(max_steps), 0, 0,
+                      float(newton_tol))
         out = {"status": status, "stats": stats}
         if plain:
             check(lib.ac_integrate_plain(self.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T),
@@ -414,7 +485,8 @@ class Workspace:
 
 
     def adjoint(self, y0, T, tape, tape_len, lam, rtol=1e-6, atol=1e-20, log_alpha=None,
-                want_glog=True, want_cells=False, want_y=False, recompute=False, stream=None):
+                want_glog=True, want_cells=False, want_y=False, recompute=False,
+                checkpoint_every=0, stream=None):
         """Discrete adjoint (ac_integrate_adjoint) of L = sum <lam, y(t_end)>
         over the recorded tape of an earlier integrate(..., tape_cap=...).
         Returns dict of device tensors: dL_dy0 [n, ns], status [n], stats
@@ -441,7 +513,8 @@ class Workspace:
         stats = torch.empty((n, NSTAT), dtype=torch.int32, device=dev)
         out = {"dL_dy0": gy0, "status": status, "stats": stats}
         g_cells = glog = yf = None
-        if want_glog or want_cells:
+        self._ensure_adjoint(int(tape.shape[1]), checkpoint_every)
+        if want_cells or (want_glog and self.adj_max_cells <= 0):
             g_cells = torch.empty((n, nr), dtype=torch.float64, device=dev)
             if want_cells:
                 out["g_cells"] = g_cells
@@ -451,7 +524,8 @@ class Workspace:
         if want_y:
             yf = torch.empty_like(y0)
             out["y_final"] = yf
-        o = IntegOpts(float(rtol), float(atol), 0.0, 5, 1, 1 if recompute else 0)
+        o = IntegOpts(float(rtol), float(atol), 0.0, 5, 1, 1 if recompute else 0,
+                      int(checkpoint_every))
         check(lib.ac_integrate_adjoint(self.handle, _ptr(log_alpha), n, _ptr(y0), _ptr(T),
                                        C.byref(o), _ptr(tape), int(tape.shape[1]),
                                        _ptr(tape_len), _ptr(lam), _ptr(yf), _ptr(gy0),
@@ -471,13 +545,32 @@ def _replay(ws, y0, T, tape, tape_len, rtol=1e-6, atol=1e-20, log_alpha=None, st
         raise ValueError("tape must be the [n, tape_cap, 2] tensor returned by integrate")
     yf = torch.empty_like(y0)
     status = torch.empty(n, dtype=torch.int32, device=y0.device)
-    o = IntegOpts(float(rtol), float(atol), 0.0, 5, 1, 1)
+    ws._ensure_adjoint(int(tape.shape[1]), ws.checkpoint_every)
+    o = IntegOpts(float(rtol), float(atol), 0.0, 5, 1, 1, int(ws.checkpoint_every))
     check(lib.ac_replay(ws.handle, _ptr(log_alpha), n, _ptr(y0), _ptr(T), C.byref(o), _ptr(tape),
                         int(tape.shape[1]), _ptr(tape_len), _ptr(yf), _ptr(status), None,
                         _stream(stream)), "ac_replay")
     return {"y_final": yf, "status": status}
 
 
+def _integrate_thermal(ws, y, T, therm, t_end, rtol=1e-6, atol=1e-20, q_max=5,
+                       max_steps=100000, h0=0.0, log_alpha=None, stream=None):
+    import torch
+    n = _thermal_args(ws.net, y, T, therm)
+    if log_alpha is not None:
+        _check_dev(log_alpha, (ws.net.n_reactions,), "log_alpha")
+    status = torch.empty(n, dtype=torch.int32, device=y.device)
+    stats = torch.empty((n, NSTAT), dtype=torch.int32, device=y.device)
+    o = IntegOpts(float(rtol), float(atol), float(h0), int(q_max), int(max_steps), 0)
+    check(lib.ac_integrate_thermal(ws.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T), _ptr(therm),
+                                   float(t_end), C.byref(o), _ptr(status), _ptr(stats),
+                                   _stream(stream)), "ac_integrate_thermal")
+    return {"status": status, "stats": stats}
+
+
+Workspace.integrate_thermal = _integrate_thermal
+Workspace.integrate_thermal.__doc__ = """ac_integrate_thermal: integrates states y
+[n, ns+1] (last entry T, in place) with temperature as a state variable."""
 Workspace.replay = _replay
 Workspace.replay.__doc__ = """ac_replay: y(t_end) replayed along a recorded tape with converged
 correctors. Returns dict of device tensors y_final [n, ns], status [n]."""

@@ -169,6 +169,14 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
     delete net;
     return fail(ac_status(code), err);
   }
+  if (desc->heat) {
+    for (int j = 0; j < desc->n_reactions; ++j)
+      if (!std::isfinite(desc->heat[j])) {
+        delete net;
+        return fail(AC_EINVAL, "reaction " + std::to_string(j) + ": heat must be finite");
+      }
+    net->host.heat.assign(desc->heat, desc->heat + desc->n_reactions);
+  }
   const ac::HostNet &H = net->host;
   Packer p;
   const size_t o_la = p.add(H.log_alpha), o_be = p.add(H.beta), o_ga = p.add(H.gamma);
@@ -178,6 +186,7 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
   const SchedOff o_jt = add_sched(p, H.jtail);
   const size_t o_h0 = p.add(H.jhead0), o_h1 = p.add(H.jhead1), o_td = p.add(H.jtaildesc);
   const size_t o_er = p.add(H.jent_row), o_ec = p.add(H.j_col);
+  const size_t o_ht = p.add(H.heat);
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();
@@ -228,6 +237,7 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
   d.jtaildesc = at<uint32_t>(b, o_td);
   d.jent_row = at<int32_t>(b, o_er);
   d.jent_col = at<int32_t>(b, o_ec);
+  d.heat = H.heat.empty() ? nullptr : at<double>(b, o_ht);
   *out = net;
   return AC_OK;
 }
@@ -410,6 +420,33 @@ ac_status ac_vjp(const ac_net *net, const double *log_alpha, int64_t n_cells, co
   return e == hipSuccess ? AC_OK : hip_fail(e, "ac_vjp launch");
 }
 
+static ac_status thermal_args(const ac_net *net, int64_t n_cells, const double *y,
+                              const double *T, const double *therm) {
+  if (ac_status s = check_cells(net, n_cells)) return s;
+  if (n_cells && (!y || !T || !therm)) return fail(AC_EINVAL, "null y, T or therm");
+  return AC_OK;
+}
+
+ac_status ac_rhs_thermal(const ac_net *net, const double *log_alpha, int64_t n_cells,
+                         const double *y, const double *T, const double *therm, double *dydt,
+                         ac_stream stream) {
+  if (ac_status s = thermal_args(net, n_cells, y, T, therm)) return s;
+  if (n_cells && !dydt) return fail(AC_EINVAL, "null dydt");
+  hipError_t e = ac::launch_rhs_thermal(net->d, log_alpha, n_cells, y, T, therm, dydt,
+                                        hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_rhs_thermal launch");
+}
+
+ac_status ac_jac_thermal(const ac_net *net, const double *log_alpha, int64_t n_cells,
+                         const double *y, const double *T, const double *therm, double *jvals,
+                         ac_stream stream) {
+  if (ac_status s = thermal_args(net, n_cells, y, T, therm)) return s;
+  if (n_cells && !jvals) return fail(AC_EINVAL, "null jvals");
+  hipError_t e = ac::launch_jac_thermal(net->d, log_alpha, n_cells, y, T, therm, jvals,
+                                        hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_jac_thermal launch");
+}
+
 // ---------------------------------------------------------- dense LU
 
 ac_status ac_lu_factor(int32_t n, int32_t lda, int64_t n_mat, double *A, int32_t *piv,
@@ -443,9 +480,12 @@ struct ac_ws {
   void *buf = nullptr;
   unsigned *queue = nullptr;
   ac::WsView W{};
-  void *adj_buf = nullptr;   // adjoint slots, grown on demand
+  void *adj_buf = nullptr;   // adjoint slots (ac_ws_reserve_adjoint)
   size_t adj_bytes = 0;
   ac::AdjView A{};
+  int adj_tape = 0;          // longest tape the reserved slots hold (0: no adjoint capacity)
+  double *rows = nullptr;    // [max_cells][n_reactions] per-cell dL/dlog alpha rows
+  int max_cells = 0;
 };
 
 extern "C" {
@@ -455,22 +495,25 @@ ac_status ac_ws_create(const ac_net *net, int32_t n_slots, ac_ws **out) {
   *out = nullptr;
   if (!net->dbuf) return fail(AC_EHIP, "network has no device copy (no GPU at creation)");
   if (n_slots < 0) return fail(AC_EINVAL, "n_slots < 0");
-  if (net->d.ns > 2 * ac::BDF_NT || ac::bdf_lds_bytes(net->d) > 160 * 1024)
+  if (net->d.ns + 1 > 2 * ac::BDF_NT || ac::bdf_lds_bytes(net->d) > 160 * 1024)
     return fail(AC_ELIMIT, "network too large for the integrator's LDS working set");
   const int resident = ac::bdf_resident_blocks(net->d);
   ac_ws *ws = new (std::nothrow) ac_ws();
   if (!ws) return fail(AC_ENOMEM, "host allocation failed");
   ws->net = net;
   ws->n_slots = n_slots ? n_slots : resident;
-  const int ns = net->d.ns, nr = net->d.nr, nnz = net->d.nnz_j;
-  const int lda = (ns + 15) / 16 * 16;
+  // every slot has room for the temperature-coupled state (ns + 1 values):
+  // Newton matrix, Jacobian pattern values plus its T column, T row and
+  // corner, difference array, pivots and permutation
+  const int ns = net->d.ns, nv = ns + 1, nr = net->d.nr, nnz = net->d.nnz_j;
+  const int lda = (nv + 15) / 16 * 16;
   auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t m_b = r256(sizeof(double) * size_t(ns) * lda);
-  const size_t j_b = r256(sizeof(double) * size_t(nnz));
+  const size_t m_b = r256(sizeof(double) * size_t(nv) * lda);
+  const size_t j_b = r256(sizeof(double) * (size_t(nnz) + 2 * size_t(ns) + 1));
   const size_t t_b = r256(sizeof(double) * size_t(std::max(1, net->host.jtail.n_slot)));
-  const size_t d_b = r256(sizeof(double) * size_t(8) * ns);
+  const size_t d_b = r256(sizeof(double) * size_t(8) * nv);
   const size_t k_b = r256(sizeof(double) * size_t(nr));
-  const size_t p_b = r256(sizeof(int) * size_t(2 * ns));
+  const size_t p_b = r256(sizeof(int) * size_t(2 * nv));
   const size_t per = m_b + j_b + t_b + d_b + k_b + p_b;
   ws->bytes = per * size_t(ws->n_slots) + 256;
   hipError_t e = hipMalloc(&ws->buf, ws->bytes);
@@ -522,6 +565,7 @@ ac_status ac_ws_create(const ac_net *net, int32_t n_slots, ac_ws **out) {
 ac_status ac_ws_destroy(ac_ws *ws) {
   if (!ws) return AC_OK;
   if (ws->adj_buf) hipFree(ws->adj_buf);
+  if (ws->rows) hipFree(ws->rows);
   hipFree(ws->buf);
   delete ws;
   return AC_OK;
@@ -552,46 +596,65 @@ ac_status ac_integrate(ac_ws *ws, const double *log_alpha, int64_t n_cells, doub
                        int32_t tape_cap, int32_t *tape_len, ac_stream stream) {
   if (ac_status s = integ_args(ws, n_cells, y, T, t_end, opts)) return s;
   if (tape && (tape_cap <= 0 || !tape_len)) return fail(AC_EINVAL, "tape needs tape_cap > 0 and tape_len");
-  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, t_end, opts->q_max, opts->max_steps};
+  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, t_end, opts->q_max, opts->max_steps,
+                   opts->newton_tol};
   ac::CellOut out{cell_status, cell_stats};
   ac::TapeView tv{reinterpret_cast<ac::AcEvent *>(tape), tape ? tape_len : nullptr, tape ? tape_cap : 0};
-  hipError_t e = ac::launch_bdf(ws->net->d, log_alpha, n_cells, y, T, P, out, tv, ws->W, ws->queue,
+  hipError_t e = ac::launch_bdf(ws->net->d, log_alpha, n_cells, y, T, nullptr, P, out, tv, ws->W,
+                                ws->queue,
                                 ws->n_slots, hipStream_t(stream));
   return e == hipSuccess ? AC_OK : hip_fail(e, "ac_integrate launch");
+}
+
+ac_status ac_integrate_thermal(ac_ws *ws, const double *log_alpha, int64_t n_cells, double *y,
+                               const double *T, const double *therm, double t_end,
+                               const ac_integ_opts *opts, int32_t *cell_status,
+                               int32_t *cell_stats, ac_stream stream) {
+  if (ac_status s = integ_args(ws, n_cells, y, T, t_end, opts)) return s;
+  if (n_cells && !therm) return fail(AC_EINVAL, "null therm");
+  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, t_end, opts->q_max, opts->max_steps,
+                   opts->newton_tol};
+  ac::CellOut out{cell_status, cell_stats};
+  ac::TapeView tv{nullptr, nullptr, 0};
+  hipError_t e = ac::launch_bdf(ws->net->d, log_alpha, n_cells, y, T, therm, P, out, tv, ws->W,
+                                ws->queue, ws->n_slots, hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_integrate_thermal launch");
 }
 
 ac_status ac_integrate_plain(ac_ws *ws, const double *log_alpha, int64_t n_cells, double *y,
                              const double *T, double t_end, const ac_integ_opts *opts,
                              int32_t *cell_status, int32_t *cell_stats, ac_stream stream) {
   if (ac_status s = integ_args(ws, n_cells, y, T, t_end, opts)) return s;
-  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, t_end, opts->q_max, opts->max_steps};
+  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, t_end, opts->q_max, opts->max_steps,
+                   opts->newton_tol};
   const int ns = ws->net->d.ns;
   for (int64_t c = 0; c < n_cells; ++c) {
     ac::CellOut out{cell_status ? cell_status + c : nullptr,
                     cell_stats ? cell_stats + c * AC_NSTAT : nullptr};
     ac::TapeView tv{nullptr, nullptr, 0};
-    hipError_t e = ac::launch_bdf(ws->net->d, log_alpha, 1, y + c * ns, T + c, P, out, tv, ws->W,
+    hipError_t e = ac::launch_bdf(ws->net->d, log_alpha, 1, y + c * ns, T + c * ws->net->d.n_cond,
+                                  nullptr, P, out, tv, ws->W,
                                   nullptr, 1, hipStream_t(stream));
     if (e != hipSuccess) return hip_fail(e, "ac_integrate_plain launch");
   }
   return AC_OK;
 }
 
-// Adjoint slots for tapes of up to tape_cap events: checkpoint store
-// (tape_cap / CK_EVERY + 1 difference arrays), the converged states of one
-// segment or, when all_states is asked for and fits, of every step, and
-// the adjoint difference array per slot.
-constexpr size_t ADJ_ALL_STATES_BUDGET = size_t(8) << 30;   // bytes over all slots
-static ac_status adj_reserve(ac_ws *ws, int tape_cap, bool all_states, hipStream_t st) {
-  const int ckcap = tape_cap / ac::CK_EVERY + 1;
-  const int ns = ws->net->d.ns;
+// Adjoint slots for tapes of up to max_tape events: a checkpoint store
+// (max_tape / every + 1 difference arrays), the converged states of one
+// segment or, with keep_states and when they fit the budget over all
+// slots, of every step, the adjoint difference array; plus per-cell rows of
+// dL/dlog alpha for max_cells cells.
+constexpr size_t ADJ_ALL_STATES_BUDGET = size_t(32) << 30;   // bytes over all slots
+
+static ac_status adj_reserve(ac_ws *ws, int max_tape, int every, bool keep_states,
+                             int max_cells) {
+  const int ns = ws->net->d.ns, nr = ws->net->d.nr;
   const size_t S = size_t(ws->n_slots);
-  if (all_states && sizeof(double) * size_t(tape_cap) * ns * S > ADJ_ALL_STATES_BUDGET)
-    all_states = false;
-  const int segcap = all_states ? tape_cap : ac::CK_EVERY;
-  if (ws->adj_buf && ws->A.ckcap >= ckcap && ws->A.segcap >= segcap &&
-      (ws->A.all_states != 0) == all_states)
-    return AC_OK;
+  const int ckcap = max_tape / every + 1;
+  bool all_states = keep_states &&
+                    sizeof(double) * size_t(max_tape) * ns * S <= ADJ_ALL_STATES_BUDGET;
+  const int segcap = all_states ? max_tape : every;
   auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t dsz = size_t(8) * ns;
   const size_t db_b = r256(sizeof(double) * dsz);
@@ -599,18 +662,28 @@ static ac_status adj_reserve(ac_ws *ws, int tape_cap, bool all_states, hipStream
   const size_t sy_b = r256(sizeof(double) * size_t(segcap) * ns);
   const size_t ce_b = r256(sizeof(int) * size_t(ckcap));
   const size_t bytes = (db_b + ck_b + sy_b + ce_b) * S;
-  if (ws->adj_buf) {
-    hipError_t e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "adjoint workspace resize (sync)");
-    hipFree(ws->adj_buf);
-    ws->adj_buf = nullptr;
-    ws->adj_bytes = 0;
-  }
+  hipError_t e = hipDeviceSynchronize();   // nothing may still use the old buffers
+  if (e != hipSuccess) return hip_fail(e, "adjoint reservation (sync)");
+  if (ws->adj_buf) hipFree(ws->adj_buf);
+  if (ws->rows) hipFree(ws->rows);
+  ws->adj_buf = nullptr;
+  ws->rows = nullptr;
+  ws->adj_bytes = 0;
+  ws->adj_tape = 0;
+  ws->max_cells = 0;
   void *p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
+  e = hipMalloc(&p, bytes);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(adjoint workspace)");
   ws->adj_buf = p;
-  ws->adj_bytes = bytes;
+  if (max_cells > 0) {
+    e = hipMalloc(reinterpret_cast<void **>(&ws->rows), sizeof(double) * size_t(max_cells) * nr);
+    if (e != hipSuccess) {
+      hipFree(ws->adj_buf);
+      ws->adj_buf = nullptr;
+      return hip_fail(e, "hipMalloc(adjoint gradient rows)");
+    }
+  }
+  ws->adj_bytes = bytes + sizeof(double) * size_t(max_cells) * nr;
   char *b = static_cast<char *>(p);
   ac::AdjView &A = ws->A;
   A.Db = reinterpret_cast<double *>(b);
@@ -625,8 +698,43 @@ static ac_status adj_reserve(ac_ws *ws, int tape_cap, bool all_states, hipStream
   A.segy_stride = sy_b / sizeof(double);
   A.ckev_stride = ce_b / sizeof(int);
   A.ckcap = ckcap;
+  A.every = every;
   A.segcap = segcap;
   A.all_states = all_states ? 1 : 0;
+  ws->adj_tape = max_tape;
+  ws->max_cells = max_cells;
+  return AC_OK;
+}
+
+ac_status ac_ws_reserve_adjoint(ac_ws *ws, const ac_adj_reserve *r) {
+  if (!ws || !r) return fail(AC_EINVAL, "null workspace or reservation");
+  const int every = r->checkpoint_every ? r->checkpoint_every : ac::CK_EVERY;
+  if (r->max_tape <= 0 || every <= 0 || r->max_cells < 0)
+    return fail(AC_EINVAL, "need max_tape > 0, checkpoint_every >= 0, max_cells >= 0");
+  return adj_reserve(ws, r->max_tape, every, r->keep_states != 0, r->max_cells);
+}
+
+ac_status ac_ws_adjoint_info(const ac_ws *ws, int32_t *max_tape, int32_t *checkpoint_every,
+                             int32_t *keeps_states, int32_t *max_cells) {
+  if (!ws) return fail(AC_EINVAL, "null workspace");
+  if (max_tape) *max_tape = ws->adj_tape;
+  if (checkpoint_every) *checkpoint_every = ws->adj_tape ? ws->A.every : 0;
+  if (keeps_states) *keeps_states = ws->adj_tape ? ws->A.all_states : 0;
+  if (max_cells) *max_cells = ws->max_cells;
+  return AC_OK;
+}
+
+// The reserved slots serve a call with this tape capacity and interval.
+static ac_status adj_capacity(const ac_ws *ws, int tape_cap, const ac_integ_opts *o) {
+  const int every = o->checkpoint_every ? o->checkpoint_every : ac::CK_EVERY;
+  if (every <= 0) return fail(AC_EINVAL, "checkpoint_every must be >= 0");
+  if (ws->adj_tape <= 0)
+    return fail(AC_ECAPACITY, "workspace has no adjoint capacity (ac_ws_reserve_adjoint)");
+  if (tape_cap > ws->adj_tape || every != ws->A.every)
+    return fail(AC_ECAPACITY, "tape longer than the workspace's adjoint reservation (" +
+                                  std::to_string(ws->adj_tape) + " events) or a checkpoint "
+                                  "interval other than the reserved " +
+                                  std::to_string(ws->A.every));
   return AC_OK;
 }
 
@@ -639,14 +747,13 @@ ac_status ac_replay(ac_ws *ws, const double *log_alpha, int64_t n_cells, const d
   if (n_cells && (!tape || !tape_len || !y_final))
     return fail(AC_EINVAL, "null tape, tape_len or y_final");
   if (!n_cells) return AC_OK;
-  hipStream_t st = hipStream_t(stream);
-  // the replay keeps its checkpoints; no converged states are stored
-  if (ac_status s = adj_reserve(ws, tape_cap, false, st)) return s;
-  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, 0.0, opts->q_max, opts->max_steps};
+  if (ac_status s = adj_capacity(ws, tape_cap, opts)) return s;
+  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, 0.0, opts->q_max, opts->max_steps,
+                   opts->newton_tol};
   ac::AdjIO io{reinterpret_cast<const ac::AcEvent *>(tape), tape_len, tape_cap, y0, T, nullptr,
                y_final, nullptr, nullptr, cell_status, cell_stats};
   hipError_t e = ac::launch_adjoint(ws->net->d, log_alpha, n_cells, io, P, ws->W, ws->A,
-                                    ws->queue, ws->n_slots, st);
+                                    ws->queue, ws->n_slots, hipStream_t(stream));
   return e == hipSuccess ? AC_OK : hip_fail(e, "ac_replay launch");
 }
 
@@ -660,20 +767,45 @@ ac_status ac_integrate_adjoint(ac_ws *ws, const double *log_alpha, int64_t n_cel
   if (tape_cap <= 0) return fail(AC_EINVAL, "tape_cap must be > 0");
   if (n_cells && (!tape || !tape_len || !lambda || !dL_dy0))
     return fail(AC_EINVAL, "null tape, tape_len, lambda or dL_dy0");
-  if (dL_dlogalpha && n_cells && !g_cells)
-    return fail(AC_EINVAL, "dL_dlogalpha needs the per-cell rows g_cells");
   hipStream_t st = hipStream_t(stream);
-  if (n_cells) {
-    if (ac_status s = adj_reserve(ws, tape_cap, opts->adj_recompute == 0, st)) return s;
-    ac::BdfParams P{opts->rtol, opts->atol, opts->h0, 0.0, opts->q_max, opts->max_steps};
-    ac::AdjIO io{reinterpret_cast<const ac::AcEvent *>(tape), tape_len, tape_cap, y0, T, lambda,
-                 y_final, dL_dy0, g_cells, cell_status, cell_stats};
-    hipError_t e = ac::launch_adjoint(ws->net->d, log_alpha, n_cells, io, P, ws->W, ws->A,
-                                      ws->queue, ws->n_slots, st);
-    if (e != hipSuccess) return hip_fail(e, "ac_integrate_adjoint launch");
+  const ac::DNet &d = ws->net->d;
+  if (!n_cells) {
+    if (dL_dlogalpha) {
+      hipError_t e = ac::launch_sum_rows(nullptr, 0, d.nr, dL_dlogalpha, false, st);
+      if (e != hipSuccess) return hip_fail(e, "ac_integrate_adjoint reduction");
+    }
+    return AC_OK;
   }
-  if (dL_dlogalpha) {
-    hipError_t e = ac::launch_sum_rows(g_cells, n_cells, ws->net->d.nr, dL_dlogalpha, st);
+  if (ac_status s = adj_capacity(ws, tape_cap, opts)) return s;
+  if (dL_dlogalpha && !g_cells && ws->max_cells <= 0)
+    return fail(AC_ECAPACITY, "dL_dlogalpha without g_cells needs the workspace's gradient rows "
+                              "(ac_adj_reserve.max_cells > 0)");
+  ac::AdjView A = ws->A;
+  if (opts->adj_recompute) A.all_states = 0;   // segments recomputed from checkpoints
+  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, 0.0, opts->q_max, opts->max_steps,
+                   opts->newton_tol};
+  // cells in chunks: all at once into the caller's rows, or max_cells at a
+  // time into the workspace's rows, each chunk's rows added to the sum in
+  // cell order (the same order as one pass over every row)
+  const int64_t chunk = g_cells || !dL_dlogalpha ? n_cells : int64_t(ws->max_cells);
+  const int nc = d.n_cond, ns = d.ns;
+  for (int64_t c0 = 0; c0 < n_cells; c0 += chunk) {
+    const int64_t m = n_cells - c0 < chunk ? n_cells - c0 : chunk;
+    double *rows = g_cells ? g_cells + c0 * d.nr : (dL_dlogalpha ? ws->rows : nullptr);
+    ac::AdjIO io{reinterpret_cast<const ac::AcEvent *>(tape) + c0 * tape_cap, tape_len + c0,
+                 tape_cap, y0 + c0 * ns, T + c0 * nc, lambda + c0 * ns,
+                 y_final ? y_final + c0 * ns : nullptr, dL_dy0 + c0 * ns, rows,
+                 cell_status ? cell_status + c0 : nullptr,
+                 cell_stats ? cell_stats + c0 * AC_NSTAT : nullptr};
+    hipError_t e = ac::launch_adjoint(d, log_alpha, m, io, P, ws->W, A, ws->queue, ws->n_slots, st);
+    if (e != hipSuccess) return hip_fail(e, "ac_integrate_adjoint launch");
+    if (dL_dlogalpha && !g_cells) {
+      e = ac::launch_sum_rows(ws->rows, m, d.nr, dL_dlogalpha, c0 > 0, st);
+      if (e != hipSuccess) return hip_fail(e, "ac_integrate_adjoint reduction");
+    }
+  }
+  if (dL_dlogalpha && g_cells) {
+    hipError_t e = ac::launch_sum_rows(g_cells, n_cells, d.nr, dL_dlogalpha, false, st);
     if (e != hipSuccess) return hip_fail(e, "ac_integrate_adjoint reduction");
   }
   return AC_OK;

@@ -24,6 +24,7 @@ struct AcEvent {
 struct BdfParams {
   double rtol, atol, h0, t_end;
   int q_max, max_steps;
+  double newton_tol;   // <= 0: max(10 eps/rtol, min(0.03, sqrt(rtol)))
 };
 
 struct CellOut {
@@ -45,16 +46,18 @@ struct WsView {
   int lda;
 };
 
-// Discrete adjoint: per-slot buffers (checkpoints every CK_EVERY accepted
-// steps, the converged states of one segment, the adjoint difference array).
+// Discrete adjoint: per-slot buffers (checkpoints every `every` accepted
+// steps, the converged states of one segment or of the whole tape, the
+// adjoint difference array). CK_EVERY is the default interval.
 constexpr int CK_EVERY = 64;
 
 struct AdjView {
   double *Db, *ck, *segY;
   int *ckev;
   size_t db_stride, ck_stride, segy_stride, ckev_stride;
-  int ckcap;
-  int segcap;       // converged states per slot: CK_EVERY, or every step of a tape
+  int ckcap;        // checkpoints per slot
+  int every;        // accepted steps between checkpoints
+  int segcap;       // converged states per slot: every, or every step of a tape
   int all_states;   // 1: the forward pass keeps every state, so no segment is recomputed
 };
 
@@ -72,14 +75,20 @@ struct AdjIO {
 
 size_t bdf_lds_bytes(const DNet &n);
 int bdf_resident_blocks(const DNet &n);
+// therm non-null selects the temperature-coupled mode (state ns + 1 per
+// cell, therm [n_cells][3] = (c_v, T_b, lambda)).
 hipError_t launch_bdf(const DNet &n, const double *la, int64_t n_cells, double *y, const double *T,
-                      const BdfParams &P, const CellOut &out, const TapeView &tv, const WsView &W,
-                      unsigned *queue, int grid, hipStream_t st);
+                      const double *therm, const BdfParams &P, const CellOut &out,
+                      const TapeView &tv, const WsView &W, unsigned *queue, int grid,
+                      hipStream_t st);
 hipError_t launch_reset_queue(unsigned *queue, hipStream_t st);
 hipError_t launch_adjoint(const DNet &n, const double *la, int64_t n_cells, const AdjIO &io,
                           const BdfParams &P, const WsView &W, const AdjView &A, unsigned *queue,
                           int grid, hipStream_t st);
-hipError_t launch_sum_rows(const double *part, int64_t rows, int nr, double *out, hipStream_t st);
+// out = (acc ? out : 0) + the rows in row order (chunks of rows summed one
+// after another equal one pass over all rows).
+hipError_t launch_sum_rows(const double *part, int64_t rows, int nr, double *out, bool acc,
+                           hipStream_t st);
 hipError_t launch_lu_factor(int n, int lda, int64_t nmat, double *A, int *piv, int *info,
                             hipStream_t st);
 hipError_t launch_lu_solve(int n, int lda, int64_t nmat, const double *LU, const int *piv,

@@ -389,6 +389,31 @@ __device__ __forceinline__ double rate_k(const Rx &r, const Env &e) {
   return rate_k(r.la, r.beta, r.gamma, r.law, e);
 }
 
+// d ln k / dT of a record at 1/T: (beta + gamma/T)/T for the modified
+// Arrhenius law, beta/T for cosmic-ray induced photons, 0 for the
+// temperature-independent laws.
+__device__ __forceinline__ double rate_dlnk_dT(const Rx &r, double invT) {
+  return r.law == AC_LAW_KOOIJ ? (r.beta + r.gamma * invT) * invT
+         : r.law == AC_LAW_CRPHOT ? r.beta * invT
+                                  : 0.0;
+}
+
+// A cell's conditions with the temperature taken from the state (the
+// temperature-coupled mode: cond[0] is not used).
+__device__ __forceinline__ Env env_with_T(const double *p, int nc, double T) {
+  Env e;
+  e.L = log(T / 300.0);
+  e.invT = 1.0 / T;
+  if (nc > 1) {
+    e.av = p[1];
+    e.lnz = log(p[2]);
+    e.lng = log(p[3]);
+  } else {
+    e.av = e.lnz = e.lng = 0.0;
+  }
+  return e;
+}
+
 __device__ __forceinline__ double reaction_rate(uint32_t pair, double k, const double *ys) {
   double r = k * ys[pair & 0xFFFFu];
   const uint32_t b = pair >> 16;
@@ -396,9 +421,32 @@ __device__ __forceinline__ double reaction_rate(uint32_t pair, double k, const d
   return r;
 }
 
+constexpr int RXU = 4;   // reaction records in flight per lane
+
+// for_reactions with the reaction's record: fn(j, k_j, record).
+template <int NT, typename F>
+__device__ __forceinline__ void for_rx(const DNet &n, const double *__restrict__ la_over,
+                                       const Env &env, F fn) {
+  for (int j0 = threadIdx.x; j0 < n.nr; j0 += RXU * NT) {
+    Rx r[RXU];
+#pragma unroll
+    for (int u = 0; u < RXU; ++u) {
+      const int j = j0 + u * NT;
+      if (j < n.nr) {
+        r[u] = load_rx(n, j);
+        if (la_over) r[u].la = la_over[j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RXU; ++u) {
+      const int j = j0 + u * NT;
+      if (j < n.nr) fn(j, rate_k(r[u], env), r[u]);
+    }
+  }
+}
+
 // For every reaction j of this thread (j = tid + m*NT), with RXU records
 // loaded before any is used: fn(j, k_j, pair).
-constexpr int RXU = 4;
 template <int NT, typename F>
 __device__ __forceinline__ void for_reactions(const DNet &n, const double *__restrict__ la_over,
                                               const Env &env, F fn) {

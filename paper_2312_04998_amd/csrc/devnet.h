@@ -36,6 +36,7 @@ struct DNet {
   DSched rhs, jac, gy, jtail;
   const uint32_t *jhead0, *jhead1, *jtaildesc;
   const int32_t *jent_row, *jent_col;   // row and column of every pattern entry
+  const double *heat;          // [nr] energy per reaction event (temperature-coupled mode) or null
 };
 
 // Launchers (kernels_chem.hip). All enqueue on `stream`; return hipError_t.
@@ -51,5 +52,15 @@ hipError_t launch_vjp(const DNet &n, const double *log_alpha, int64_t n_cells, c
                       const double *T, const double *v, double *gy, double *g_logalpha,
                       double *part, int part_rows, hipStream_t stream);
 size_t rhs_lds_bytes(const DNet &n);
+
+// Temperature-coupled mode (kernels_thermal.hip): state [n_cells][ns + 1],
+// therm [n_cells][3] = (c_v, T_b, lambda); the Jacobian's values per cell
+// are the pattern values, the T column, the T row and the corner.
+hipError_t launch_rhs_thermal(const DNet &n, const double *la, int64_t n_cells, const double *y,
+                              const double *cond, const double *therm, double *dydt,
+                              hipStream_t stream);
+hipError_t launch_jac_thermal(const DNet &n, const double *la, int64_t n_cells, const double *y,
+                              const double *cond, const double *therm, double *jvals,
+                              hipStream_t stream);
 
 }  // namespace ac

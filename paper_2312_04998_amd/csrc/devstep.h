@@ -50,6 +50,16 @@ struct CellCtx {
   double *rs, *part, *scr, *tmp, *red;   // LDS: rate block + slots | LU panel | solve block
   int *redi, *ipiv;
   int cnt[ST_N];   // per-cell counters (identical on every thread)
+  int lu_info = 0; // 0, or 1 + the first exactly-zero pivot of the last factorisation
+  // temperature-coupled mode: the cell's conditions (cond[0] unused), its
+  // heat capacity, background temperature and relaxation rate, the
+  // log-prefactor override, and the Jacobian's T column, T row and corner
+  // (slot, global, after the pattern values)
+  const double *cond = nullptr;
+  int nc = 1;
+  double cv = 1.0, Tb = 0.0, lam = 0.0;
+  const double *la_over = nullptr;
+  double *Jaux = nullptr;
 };
 
 template <int NT>
@@ -157,8 +167,114 @@ __device__ __forceinline__ void cell_factor(CellCtx &cx, double c) {
         cx.M[size_t(ri[u]) * lda + ci[u]] = (ri[u] == ci[u] ? 1.0 : 0.0) - c * jv[u];
   }
   __syncthreads();
-  wg_lu<NT>(cx.M, lda, ns, cx.piv, cx.perm, cx.scr, cx.red, cx.redi, cx.ipiv);
+  cx.lu_info = wg_lu<NT>(cx.M, lda, ns, cx.piv, cx.perm, cx.scr, cx.red, cx.redi, cx.ipiv);
   cx.cnt[ST_LU]++;
+}
+
+// ---------------------------------------------- temperature as a state
+// State (n_1..n_ns, T); the coefficients follow the state's T and
+// dT/dt = (sum_j heat_j R_j) / c_v - lambda (T - T_b) (codes that solve
+// temperature and abundances together, Sec. 5).
+
+// f = (S R(y), dT/dt), coefficients recomputed at T = y[ns]; y, f in LDS.
+template <int NT>
+__device__ __forceinline__ void cell_rhs_th(CellCtx &cx, const double *y, double *f) {
+  const DNet &n = *cx.n;
+  const int ns = n.ns;
+  const double T = y[ns];
+  const Env env = env_with_T(cx.cond, cx.nc, T);
+  const double *heat = n.heat;
+  double hsum = 0.0;
+  for_rx<NT>(n, cx.la_over, env, [&](int j, double kj, const Rx &r) {
+    const double rj = reaction_rate(r.pair, kj, y);
+    cx.rs[j] = rj;
+    if (heat) hsum += heat[j] * rj;
+  });
+  __syncthreads();
+  segsum_chunks<NT, LAYOUT_SELL, false, false>(n.rhs, cx.rs, y, cx.part, f);
+  __syncthreads();
+  segsum_finish<NT, false>(n.rhs, cx.part, f);
+  const double q = wg_sum<NT>(hsum, cx.red);
+  if (threadIdx.x == 0) f[ns] = q / cx.cv - cx.lam * (T - cx.Tb);
+  __syncthreads();
+  cx.cnt[ST_RHS]++;
+}
+
+// Jacobian at y (LDS) with the coefficients at T = y[ns]: pattern values
+// into the slot (as cell_jac, with the coefficients refreshed in the slot),
+// then the T column sum_j S_ij R_j dln k_j/dT, the T row
+// sum_{slots of a} heat_j dR_j/dn_a / c_v and the corner
+// sum_j heat_j R_j dln k_j/dT / c_v - lambda into cx.Jaux.
+template <int NT>
+__device__ __forceinline__ void cell_jac_th(CellCtx &cx, const double *y) {
+  const DNet &n = *cx.n;
+  const int ns = n.ns;
+  const double T = y[ns];
+  const Env env = env_with_T(cx.cond, cx.nc, T);
+  const double *heat = n.heat;
+  double csum = 0.0;
+  for_rx<NT>(n, cx.la_over, env, [&](int j, double kj, const Rx &r) {
+    cx.kg[j] = kj;
+    const double w = reaction_rate(r.pair, kj, y) * rate_dlnk_dT(r, env.invT);
+    cx.rs[j] = w;
+    if (heat) csum += heat[j] * w;
+  });
+  __syncthreads();
+  segsum_chunks<NT, LAYOUT_SELL, false, false>(n.rhs, cx.rs, y, cx.part, cx.Jaux);
+  __syncthreads();
+  segsum_finish<NT, false>(n.rhs, cx.part, cx.Jaux);
+  __syncthreads();
+  for (int j = threadIdx.x; j < n.nr; j += NT) cx.rs[j] = heat ? cx.kg[j] * heat[j] / cx.cv : 0.0;
+  __syncthreads();
+  segsum_chunks<NT, LAYOUT_SELL, false, true>(n.gy, cx.rs, y, cx.part, cx.Jaux + ns);
+  __syncthreads();
+  segsum_finish<NT, false>(n.gy, cx.part, cx.Jaux + ns);
+  const double corner = wg_sum<NT>(csum, cx.red) / cx.cv - cx.lam;
+  if (threadIdx.x == 0) cx.Jaux[2 * ns] = corner;
+  __syncthreads();
+  cell_jac<NT>(cx, y);   // pattern values with the refreshed coefficients
+}
+
+// M = I - c J over the coupled state (ns + 1), then LU.
+template <int NT>
+__device__ __forceinline__ void cell_factor_th(CellCtx &cx, double c) {
+  const DNet &n = *cx.n;
+  const int ns = n.ns, nv = ns + 1, lda = cx.lda;
+  for (int e = threadIdx.x; e < nv * lda; e += NT) {
+    const int i = e / lda, a = e - i * lda;
+    cx.M[e] = (i == a) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n.nnz_j; e += NT) {
+    const int ri = n.jent_row[e], ci = n.jent_col[e];
+    cx.M[size_t(ri) * lda + ci] = (ri == ci ? 1.0 : 0.0) - c * cx.Jg[e];
+  }
+  for (int i = threadIdx.x; i < ns; i += NT) {
+    cx.M[size_t(i) * lda + ns] = -c * cx.Jaux[i];
+    cx.M[size_t(ns) * lda + i] = -c * cx.Jaux[ns + i];
+  }
+  if (threadIdx.x == 0) cx.M[size_t(ns) * lda + ns] = 1.0 - c * cx.Jaux[2 * ns];
+  __syncthreads();
+  cx.lu_info = wg_lu<NT>(cx.M, lda, nv, cx.piv, cx.perm, cx.scr, cx.red, cx.redi, cx.ipiv);
+  cx.cnt[ST_LU]++;
+}
+
+template <int NT, bool TH>
+__device__ __forceinline__ void cell_rhs_any(CellCtx &cx, const double *y, double *f) {
+  if (TH) cell_rhs_th<NT>(cx, y, f);
+  else cell_rhs<NT>(cx, y, f);
+}
+
+template <int NT, bool TH>
+__device__ __forceinline__ void cell_jac_any(CellCtx &cx, const double *y) {
+  if (TH) cell_jac_th<NT>(cx, y);
+  else cell_jac<NT>(cx, y);
+}
+
+template <int NT, bool TH>
+__device__ __forceinline__ void cell_factor_any(CellCtx &cx, double c) {
+  if (TH) cell_factor_th<NT>(cx, c);
+  else cell_factor<NT>(cx, c);
 }
 
 // Resampling matrix for a step change by `factor` (Shampine & Reichelt

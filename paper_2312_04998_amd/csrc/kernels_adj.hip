@@ -19,7 +19,7 @@
 //
 // One persistent workgroup handles one cell at a time (device queue). It
 // replays the tape forward once with converged correctors, keeping the
-// difference array every CK_EVERY accepted steps (the replay of a segment
+// difference array every A.every accepted steps (the replay of a segment
 // depends only on its checkpoint, so a recomputed segment repeats the first
 // pass bit for bit); the reverse sweep then
 // walks the segments backwards, recomputing each segment forward from its
@@ -257,13 +257,14 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
         for (int m = 1; m < NDROW; ++m) cx.D[size_t(m) * ns + x] = 0.0;
       }
       __syncthreads();
-      // forward replay with checkpoints every CK_EVERY accepted steps
-      int nck = 0, nstep = 0;   // nck <= cap / CK_EVERY + 1 = A.ckcap since nstep <= nev <= cap
+      // forward replay with checkpoints every A.every accepted steps
+      const int every = A.every;
+      int nck = 0, nstep = 0;   // nck <= cap / every + 1 <= A.ckcap since nstep <= nev <= cap
       double cM = 0.0;
       for (int e = 0; e < nev; ++e) {
         const AcEvent E = ev[e];
         if (E.type == EV_STEP) {
-          if (nstep % CK_EVERY == 0) {
+          if (nstep % every == 0) {
             double *dst = ck + size_t(nck) * dsz;
             for (size_t i = threadIdx.x; i < dsz; i += NT) dst[i] = cx.D[i];
             if (threadIdx.x == 0) ckev[nck] = e;
@@ -295,9 +296,9 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
         int i = 0;
         const double *sy = segY;
         if (A.all_states) {
-          // the forward pass kept them: segment s is steps s*CK_EVERY ...
-          sy = segY + size_t(s) * CK_EVERY * ns;
-          i = s + 1 < nck ? CK_EVERY : nstep - s * CK_EVERY;
+          // the forward pass kept them: segment s is steps s*every ...
+          sy = segY + size_t(s) * every * ns;
+          i = s + 1 < nck ? every : nstep - s * every;
         } else {
           const double *src = ck + size_t(s) * dsz;
           for (size_t k = threadIdx.x; k < dsz; k += NT) cx.D[k] = src[k];

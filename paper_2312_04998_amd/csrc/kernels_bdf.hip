@@ -41,14 +41,18 @@ __device__ __forceinline__ void tape_put(const TapeView &tv, int64_t cell, int &
   ++len;
 }
 
-template <int NT>
+// TH: temperature-coupled mode, the state is (n_1..n_ns, T) and therm
+// holds (c_v, T_b, lambda) per cell; otherwise T is held at the cell's
+// conditions. ns below is the length of the state vector.
+template <int NT, bool TH>
 __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ la_over,
                                             int64_t n_cells, double *__restrict__ y,
-                                            const double *__restrict__ T, BdfParams P,
+                                            const double *__restrict__ T,
+                                            const double *__restrict__ therm, BdfParams P,
                                             CellOut out, TapeView tv, WsView W,
                                             unsigned *queue) {
   extern __shared__ double sm[];
-  const int ns = n.ns, nr = n.nr;
+  const int ns = n.ns + (TH ? 1 : 0), nr = n.nr;
   double *f = sm, *yn = f + ns, *dd = yn + ns, *psi = dd + ns, *scl = psi + ns, *yp = scl + ns,
          *dy = yp + ns, *tmp = dy + ns, *scr = tmp + ns;
   double *rs = scr, *part = scr + nr;        // RHS use of the scratch region
@@ -75,8 +79,13 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
   cx.red = red;
   cx.redi = redi;
   cx.ipiv = ipiv;
+  cx.nc = n.n_cond;
+  cx.la_over = la_over;
+  cx.Jaux = cx.Jg + n.nnz_j;
   const double rtol = P.rtol, atol = P.atol, t_end = P.t_end;
-  const double tol = fmax(10.0 * 2.220446049250313e-16 / rtol, fmin(0.03, sqrt(rtol)));
+  const double tol = P.newton_tol > 0.0
+                         ? P.newton_tol
+                         : fmax(10.0 * 2.220446049250313e-16 / rtol, fmin(0.03, sqrt(rtol)));
 
   for (int64_t iter = 0;; ++iter) {
     if (threadIdx.x == 0)
@@ -95,12 +104,23 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
       if (!(isfinite(v) && v >= 0.0)) bad = true;
     }
     bad = wg_any<NT>(bad, red) || !cell_env_ok(T, cell, n.n_cond);
+    if (TH) {
+      const double *th = therm + cell * 3, Tc = ycell[n.ns];
+      bad = bad || !(Tc > 0.0 && isfinite(th[0]) && th[0] > 0.0 && isfinite(th[1]) &&
+                     th[1] > 0.0 && isfinite(th[2]) && th[2] >= 0.0);
+      cx.cond = T + cell * n.n_cond;
+      cx.cv = th[0];
+      cx.Tb = th[1];
+      cx.lam = th[2];
+    }
     int status = AC_CELL_OK, q = 1, steps = 0;
     const bool run = !bad && t_end > 0.0;
     if (bad) status = AC_CELL_BADINPUT;
     if (run) {
-      const Env env = cell_env(T, cell, n.n_cond);
-      for_reactions<NT>(n, la_over, env, [&](int j, double kj, uint32_t) { cx.kg[j] = kj; });
+      if (!TH) {
+        const Env env = cell_env(T, cell, n.n_cond);
+        for_reactions<NT>(n, la_over, env, [&](int j, double kj, uint32_t) { cx.kg[j] = kj; });
+      }
       for (int x = threadIdx.x; x < ns; x += NT) {
         const double v = ycell[x];
         yn[x] = v;
@@ -108,7 +128,7 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
         for (int m = 1; m < NDROW; ++m) cx.D[size_t(m) * ns + x] = 0.0;
       }
       __syncthreads();
-      cell_rhs<NT>(cx, yn, f);
+      cell_rhs_any<NT, TH>(cx, yn, f);
       // first step (Hairer, Norsett & Wanner, Sec. II.4, order 1)
       double h;
       if (P.h0 > 0.0) {
@@ -122,7 +142,7 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
         if (h0 > t_end) h0 = t_end;
         for (int x = threadIdx.x; x < ns; x += NT) yp[x] = yn[x] + h0 * f[x];
         __syncthreads();
-        cell_rhs<NT>(cx, yp, dy);
+        cell_rhs_any<NT, TH>(cx, yp, dy);
         for (int x = threadIdx.x; x < ns; x += NT) dy[x] -= f[x];
         __syncthreads();
         const double d2 = wg_rms<NT>(dy, 1.0, scl, ns, red) / h0;
@@ -133,9 +153,11 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
       tape_put(tv, cell, tlen, EV_INIT, 1, h);
       for (int x = threadIdx.x; x < ns; x += NT) cx.D[size_t(ns) + x] = h * f[x];
       __syncthreads();
-      cell_jac<NT>(cx, yn);
+      cell_jac_any<NT, TH>(cx, yn);
 
       int n_equal = 0;
+      // why the last attempt was rejected, the status if h falls below h_min
+      int last_fail = AC_CELL_HMIN;
       bool lu_valid = false;
       double cM = 0.0;   // c of the factored Newton matrix
       double t = 0.0, h_abs = h;
@@ -151,7 +173,7 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
         bool failed = false;
         for (;;) {   // attempts
           if (h_abs < hmin) {
-            status = AC_CELL_HMIN;
+            status = last_fail;
             failed = true;
             break;
           }
@@ -180,10 +202,10 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
           }
           __syncthreads();
           const double c = h / alph_q;
-          bool conv = false;
+          bool conv = false, nonfin = false;
           for (;;) {
             if (!lu_valid || fabs(c / cM - 1.0) > 0.3) {
-              cell_factor<NT>(cx, c);
+              cell_factor_any<NT, TH>(cx, c);
               lu_valid = true;
               cM = c;
             }
@@ -197,11 +219,12 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
             double prev = 0.0;
             int it;
             for (it = 0; it < NEWTON_MAXITER; ++it) {
-              cell_rhs<NT>(cx, yn, f);
+              cell_rhs_any<NT, TH>(cx, yn, f);
               bool nonfinite = false;
               for (int x = threadIdx.x; x < ns; x += NT)
                 if (!isfinite(f[x])) nonfinite = true;
-              if (wg_any<NT>(nonfinite, red)) break;
+              nonfin = wg_any<NT>(nonfinite, red);
+              if (nonfin) break;
               for (int x = threadIdx.x; x < ns; x += NT) dy[x] = c * f[x] - psi[x] - dd[x];
               __syncthreads();
               wg_solve<NT>(cx.M, cx.lda, ns, cx.perm, dy, cx.tmp, false, cx.scr);
@@ -230,11 +253,13 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
             n_iter = it + 1;
             cx.cnt[ST_NEWTON] += it < NEWTON_MAXITER ? it + 1 : NEWTON_MAXITER;
             if (conv || jac_fresh) break;
-            cell_jac<NT>(cx, yp);
+            cell_jac_any<NT, TH>(cx, yp);
             jac_fresh = true;
             lu_valid = false;
           }
           if (!conv) {
+            last_fail = cx.lu_info ? AC_CELL_SINGULAR : nonfin ? AC_CELL_NONFINITE
+                                                               : AC_CELL_NEWTON_FAIL;
             h_abs *= 0.5;
             rescale_diffs<NT>(cx, q, 0.5, ns);
             tape_put(tv, cell, tlen, EV_RESCALE, q, 0.5);
@@ -247,6 +272,7 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
           __syncthreads();
           en = wg_rms<NT>(dd, bdf_errc(q), scl, ns, red);
           if (en > 1.0) {
+            last_fail = AC_CELL_HMIN;
             const double factor = fmax(MIN_FACTOR, safety * pow_neg(en, 1.0 / (q + 1)));
             h_abs *= factor;
             rescale_diffs<NT>(cx, q, factor, ns);
@@ -350,17 +376,20 @@ __global__ __launch_bounds__(NT) void k_lu_solve(int n, int lda, int64_t nmat, c
 
 // ---------------------------------------------------------------- launch
 
+// LDS of the integrator and adjoint kernels: 8 state vectors (room for the
+// temperature of the coupled mode), the shared scratch region, reductions.
 size_t bdf_lds_bytes(const DNet &n) {
-  return sizeof(double) * (size_t(8) * n.ns + bdf_scratch_doubles(n) + 16 + 3 * (QMAX + 1) * (QMAX + 1)) +
+  return sizeof(double) * (size_t(8) * (n.ns + 1) + bdf_scratch_doubles(n) + 16 +
+                           3 * (QMAX + 1) * (QMAX + 1)) +
          sizeof(int) * (16 + 9 * PW + 2);
 }
 
 int bdf_resident_blocks(const DNet &n) {
   const size_t lds = bdf_lds_bytes(n);
-  if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(k_bdf<BDF_NT>),
+  if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(k_bdf<BDF_NT, false>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bdf<BDF_NT>, BDF_NT, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bdf<BDF_NT, false>, BDF_NT, lds) !=
           hipSuccess || per_cu <= 0)
     per_cu = 1;
   int dev = 0, cus = 0;
@@ -370,16 +399,18 @@ int bdf_resident_blocks(const DNet &n) {
 }
 
 hipError_t launch_bdf(const DNet &n, const double *la, int64_t n_cells, double *y, const double *T,
-                      const BdfParams &P, const CellOut &out, const TapeView &tv, const WsView &W,
-                      unsigned *queue, int grid, hipStream_t st) {
+                      const double *therm, const BdfParams &P, const CellOut &out,
+                      const TapeView &tv, const WsView &W, unsigned *queue, int grid,
+                      hipStream_t st) {
   if (n_cells == 0) return hipSuccess;
   const size_t lds = bdf_lds_bytes(n);
-  if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(k_bdf<BDF_NT>),
+  auto kern = therm ? k_bdf<BDF_NT, true> : k_bdf<BDF_NT, false>;
+  if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (queue) hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, queue);
   const int g = int(n_cells < grid ? n_cells : grid);
-  hipLaunchKernelGGL(k_bdf<BDF_NT>, dim3(g), dim3(BDF_NT), lds, st, n, la, n_cells, y, T, P, out,
-                     tv, W, queue);
+  hipLaunchKernelGGL(kern, dim3(g), dim3(BDF_NT), lds, st, n, la, n_cells, y, T, therm, P, out, tv,
+                     W, queue);
   return hipGetLastError();
 }
 

@@ -505,11 +505,13 @@ __global__ __launch_bounds__(RED_NT) void k_fill(double *__restrict__ p, int64_t
     p[i] = v;
 }
 
+// out[j] = (acc ? out[j] : 0) + rows added one by one in row order, so that
+// sums taken in consecutive chunks of rows equal one sum over all of them.
 __global__ __launch_bounds__(RED_NT) void k_sum_rows(const double *__restrict__ part, int rows,
-                                                     int nr, double *__restrict__ out) {
+                                                     int nr, double *__restrict__ out, int acc) {
   const int j = blockIdx.x * RED_NT + threadIdx.x;
   if (j >= nr) return;
-  double s = 0.0;
+  double s = acc ? out[j] : 0.0;
   for (int r = 0; r < rows; ++r) s += part[size_t(r) * nr + j];
   out[j] = s;
 }
@@ -667,18 +669,20 @@ static hipError_t vjp_nt(const DNet &n, const double *la, int64_t n_cells, const
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !g_logalpha) return e;
   hipLaunchKernelGGL(k_sum_rows, dim3((n.nr + RED_NT - 1) / RED_NT), dim3(RED_NT), 0, st, part, g,
-                     n.nr, g_logalpha);
+                     n.nr, g_logalpha, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_sum_rows(const double *part, int64_t rows, int nr, double *out, hipStream_t st) {
+hipError_t launch_sum_rows(const double *part, int64_t rows, int nr, double *out, bool acc,
+                           hipStream_t st) {
   if (rows == 0) {
+    if (acc) return hipSuccess;
     hipLaunchKernelGGL(k_fill, dim3((nr + RED_NT - 1) / RED_NT), dim3(RED_NT), 0, st, out,
                        int64_t(nr), 0.0);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_sum_rows, dim3((nr + RED_NT - 1) / RED_NT), dim3(RED_NT), 0, st, part,
-                     int(rows), nr, out);
+                     int(rows), nr, out, acc ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -708,7 +712,7 @@ hipError_t launch_vjp(const DNet &n, const double *la, int64_t n_cells, const do
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !g_logalpha) return e;
     hipLaunchKernelGGL(k_sum_rows, dim3((n.nr + RED_NT - 1) / RED_NT), dim3(RED_NT), 0, st, part,
-                       g, n.nr, g_logalpha);
+                       g, n.nr, g_logalpha, 0);
     return hipGetLastError();
   }
 #define CALL(NT) vjp_nt<NT>(n, la, n_cells, y, T, v, gy, g_logalpha, part, part_rows, st)

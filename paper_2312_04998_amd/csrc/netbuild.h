@@ -69,6 +69,8 @@ struct HostNet {
   // parameters in the form ln k = ln alpha + beta' ln(T/300) - gamma' X + Y
   // (see devchem.h rate_k)
   std::vector<int8_t> law;
+  // energy released per reaction event (temperature-coupled mode), or empty
+  std::vector<double> heat;
   std::vector<uint32_t> rpair;        // reactant a | b << 16, 0xFFFF = none
   // per reaction, in three planes of nr 16-byte words: (ln alpha, beta'),
   // (gamma', rpair, law), and the net column of S as up to 8 16-bit

@@ -63,6 +63,7 @@ class Network:
     names: List[str]
     rtype: np.ndarray
     law: Optional[np.ndarray] = None   # int8 [n_reactions] rate-law code, None = all Kooij
+    heat: Optional[np.ndarray] = None  # float64 [n_reactions] erg per reaction event, or None
 
     @property
     def n_species(self) -> int:
@@ -79,7 +80,8 @@ class Network:
                        self.alpha[idx].copy(), self.beta[idx].copy(),
                        self.gamma[idx].copy(), self.composition.copy(),
                        list(self.names), self.rtype[idx].copy(),
-                       None if self.law is None else self.law[idx].copy())
+                       None if self.law is None else self.law[idx].copy(),
+                       None if self.heat is None else self.heat[idx].copy())
 
 
 def network_from_lists(n_species: int,
@@ -482,6 +484,40 @@ def make_conditions(T: np.ndarray, seed: int, Av_range=(0.1, 20.0), zeta_range=(
     out[:, 2] = np.exp(rng.uniform(np.log(zeta_range[0]), np.log(zeta_range[1]), n))
     out[:, 3] = np.exp(rng.uniform(np.log(G0_range[0]), np.log(G0_range[1]), n))
     return out
+
+
+# --------------------------------------------------------------------------
+# temperature as a state: reaction heats and per-cell thermal parameters
+# --------------------------------------------------------------------------
+
+K_BOLTZMANN = 1.380649e-16   # erg / K
+
+
+def species_enthalpies(n_species: int, seed: int, scale_K: float = 50.0) -> np.ndarray:
+    """Seeded per-species energies h_i = k_B theta_i with theta_i uniform on
+    (-scale_K, scale_K) K [erg]. Reaction heats built from them conserve
+    c_v T + sum_i h_i n_i exactly when nothing else heats or cools."""
+    rng = np.random.default_rng(seed + 3571)
+    return K_BOLTZMANN * rng.uniform(-scale_K, scale_K, n_species)
+
+
+def with_heat(net: Network, h: np.ndarray) -> Network:
+    """A copy of ``net`` whose reaction j releases heat_j = sum over its
+    reactants of h minus the sum over its products (erg per event, the
+    reaction's energy balance for species energies h)."""
+    heat = np.zeros(net.n_reactions)
+    for j in range(net.n_reactions):
+        heat[j] = sum(h[a] for a in net.reactants[j] if a >= 0) - \
+            sum(h[p] for p in net.products[j] if p >= 0)
+    return dataclasses.replace(net, heat=heat)
+
+
+def thermal_params(n_H: np.ndarray, T0: np.ndarray, lam: float = 1e-11) -> np.ndarray:
+    """Per-cell (c_v, T_b, lambda): the heat capacity of an ideal monatomic
+    gas of density n_H (1.5 k_B n_H), the background temperature T0 the gas
+    relaxes to, and the relaxation rate lambda [1/s]."""
+    return np.stack([1.5 * K_BOLTZMANN * np.asarray(n_H, np.float64), np.asarray(T0, np.float64),
+                     np.full(len(T0), float(lam))], 1)
 
 
 # --------------------------------------------------------------------------

@@ -245,3 +245,68 @@ def test_adjoint_kept_states_equal_recomputed(acm, oracle_mod, which):
     sa, sb = a["stats"].cpu().numpy(), b["stats"].cpu().numpy()
     assert np.array_equal(sa[:, 0], sb[:, 0])          # steps reversed
     assert (sa[:, 3] < sb[:, 3]).all()                  # fewer replay Newton iterations
+
+
+def test_adjoint_gradient_rows_in_workspace_and_checkpoint_interval(acm, oracle_mod):
+    """The summed dL/dlog alpha from the workspace's own rows (no per-cell
+    buffer; 5 cells in chunks of 2) equals the sum of the caller's per-cell
+    rows bit for bit, and so do the gradients with checkpoints every 16
+    steps (segments recomputed) and every 64 (states kept)."""
+    import torch
+    net, cells = synthnet.workload("tiny", n_cells=5)
+    t_end = 1e4 * YEAR_S
+    ref = oracle_mod.bdf(net, cells.y0, cells.T, t_end, tape_cap=8000)
+    N = acm.Network.from_synth(net)
+    lam = np.random.default_rng(31).standard_normal(cells.y0.shape)
+    args = (_t(cells.y0), _t(cells.T), acm.tape_from_numpy(ref["tape"]),
+            _t(ref["tape_len"], np.int32), _t(lam))
+    ws_a = acm.Workspace(N, n_slots=2)
+    a = ws_a.adjoint(*args, want_cells=True)
+    ws_b = acm.Workspace(N, n_slots=2, adj_max_tape=8000, adj_max_cells=2)
+    b = ws_b.adjoint(*args)
+    assert "g_cells" not in b
+    assert torch.equal(a["dL_dlogalpha"], b["dL_dlogalpha"]) and torch.equal(a["dL_dy0"], b["dL_dy0"])
+    ws_c = acm.Workspace(N, n_slots=2, adj_max_tape=8000, checkpoint_every=16)
+    c = ws_c.adjoint(*args, want_cells=True, recompute=True, checkpoint_every=16)
+    for k in ("dL_dy0", "g_cells", "dL_dlogalpha"):
+        assert torch.equal(a[k], c[k]), k
+
+
+def test_adjoint_refuses_without_reservation(acm, oracle_mod):
+    """ac_integrate_adjoint allocates nothing: a tape longer than the
+    workspace's reservation, or a different checkpoint interval, is refused
+    with AC_ECAPACITY before any launch."""
+    import ctypes as C
+    net, cells = synthnet.workload("tiny", n_cells=2)
+    ref = oracle_mod.bdf(net, cells.y0, cells.T, 1e3 * YEAR_S, tape_cap=4000)
+    N = acm.Network.from_synth(net)
+    ws = acm.Workspace(N, n_slots=2, adj_max_tape=100)
+    tape = acm.tape_from_numpy(ref["tape"])
+    tl = _t(ref["tape_len"], np.int32)
+    y0, T, lam = _t(cells.y0), _t(cells.T), _t(np.ones_like(cells.y0))
+    gy = _t(np.zeros_like(cells.y0))
+    for cap, every in ((4000, 0), (100, 32)):
+        o = acm.IntegOpts(1e-6, 1e-20, 0.0, 5, 1, 0, every, 0.0)
+        st = acm.lib.ac_integrate_adjoint(ws.handle, None, 2, y0.data_ptr(), T.data_ptr(),
+                                          C.byref(o), tape.data_ptr(), cap, tl.data_ptr(),
+                                          lam.data_ptr(), None, gy.data_ptr(), None, None, None,
+                                          None, None)
+        assert st == acm.AC_ECAPACITY, (cap, every, acm.last_error())
+
+
+def test_newton_tolerance_option(acm, oracle_mod):
+    """A looser corrector tolerance, passed to both sides, still gives the
+    oracle's step counts (within 2 % + 3) and results within its rerun
+    envelope."""
+    from test_gpu_integrate import _agree, oracle_with_envelope
+    net, cells = synthnet.workload("tiny", n_cells=3)
+    N = acm.Network.from_synth(net)
+    ws = acm.Workspace(N, n_slots=3)
+    y = _t(cells.y0)
+    out = ws.integrate(y, _t(cells.T), 1e4 * YEAR_S, newton_tol=1e-2)
+    ref, env, _ = oracle_with_envelope(oracle_mod, net, cells.y0, cells.T, 1e4 * YEAR_S, k=8,
+                                       newton_tol=1e-2)
+    st = out["stats"].cpu().numpy()
+    assert out["status"].cpu().tolist() == ref["status"].tolist() == [0, 0, 0]
+    assert np.all(np.abs(st[:, 0] - ref["stats"][:, 0]) <= 0.02 * ref["stats"][:, 0] + 3)
+    assert _agree(y.cpu().numpy(), ref["y"], envelope=env).all()

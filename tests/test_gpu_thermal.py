@@ -1,0 +1,138 @@
+"""GPU parity of the temperature-coupled mode (temperature as a state
+variable, Sec. 5): RHS and Jacobian (pattern values, T column, T row,
+corner) against the oracle, and the coupled integrator against the oracle's
+(within the spread of perturbed oracle reruns), a closed form and the
+conserved energy."""
+import concurrent.futures as cf
+import dataclasses
+
+import numpy as np
+import pytest
+
+import synthnet
+from conftest import YEAR_S, network_from
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def acm(torch_dev):
+    import paper_2312_04998_amd as acm
+    return acm
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float64)).cuda()
+
+
+def _thermal(net0, n, seed, lam=0.0, scale_K=50.0):
+    h = synthnet.species_enthalpies(net0.n_species, seed, scale_K)
+    net = synthnet.with_heat(net0, h)
+    cells = synthnet.make_cells(net, n, synthnet.SEED_BASE + 12)
+    y = np.concatenate([cells.y0, cells.T[:, None]], 1)
+    th = synthnet.thermal_params(cells.n_H, cells.T, lam)
+    return net, h, cells, y, th
+
+
+@pytest.mark.parametrize("laws", [False, True])
+def test_thermal_rhs_and_jacobian(acm, oracle_mod, medium_net, laws):
+    net0 = synthnet.with_rate_laws(medium_net, 5) if laws else medium_net
+    net, h, cells, y, th = _thermal(net0, 37, 4, lam=1e-11)
+    y[:, -1] *= np.linspace(0.7, 1.6, 37)
+    cond = synthnet.make_conditions(cells.T, 9) if laws else cells.T
+    N = acm.Network.from_synth(net)
+    yd, cd, td = _t(y), _t(cond), _t(th)
+    f = _t(np.zeros_like(y))
+    acm.ac_rhs_thermal(N, None, yd, cd, td, f)
+    ref, ab = oracle_mod.rhs_thermal(net, y, cond, th, with_abs=True)
+    assert np.all(np.abs(f.cpu().numpy() - ref) <= 1e-12 * ab)
+    m = 5
+    jv = _t(np.zeros((m, N.nnz_j + 2 * net.n_species + 1)))
+    acm.ac_jac_thermal(N, None, yd[:m], cd[:m], td[:m], jv)
+    jv = jv.cpu().numpy()
+    J = oracle_mod.jac_thermal(net, y[:m], cond[:m], th[:m])
+    ns, nnz = net.n_species, N.nnz_j
+    rp, col = N.jac_pattern()
+    rows = np.repeat(np.arange(ns), np.diff(rp))
+    _, abJ = oracle_mod.jac_dense(net, y[:m, :-1], y[:m, -1], with_abs=True)
+    assert np.all(np.abs(jv[:, :nnz] - J[:, rows, col]) <= 1e-12 * abJ[:, rows, col])
+    # T column, T row and corner: sums of mixed-sign terms, held to 1e-12 of
+    # the largest term magnitude of their row or column
+    for got, want in ((jv[:, nnz:nnz + ns], J[:, :ns, ns]), (jv[:, nnz + ns:nnz + 2 * ns], J[:, ns, :ns]),
+                      (jv[:, -1:], J[:, ns:, ns])):
+        scale = np.abs(want).max(1, keepdims=True)
+        assert np.all(np.abs(got - want) <= 1e-10 * np.abs(want) + 1e-12 * scale)
+
+
+def test_thermal_integration_matches_oracle(acm, oracle_mod, tiny):
+    """50-species network with reaction heats of +-300 K per event and
+    relaxation, 4 cells to 1e4 yr, against the oracle within 10x the spread
+    of 8 reruns with y0 perturbed by 1e-15 and alpha by 1e-14 relative."""
+    net0, _ = tiny
+    net, h, cells, y, th = _thermal(net0, 4, 6, lam=3e-12, scale_K=300.0)
+    t_end = 1e4 * YEAR_S
+    N = acm.Network.from_synth(net)
+    ws = acm.Workspace(N, n_slots=4)
+    yd = _t(y)
+    out = ws.integrate_thermal(yd, _t(cells.T), _t(th), t_end)
+    rng = np.random.default_rng(12345)
+    jobs = [(net, y)]
+    for _ in range(8):
+        pnet = dataclasses.replace(net, alpha=net.alpha * (1 + 1e-14 * rng.standard_normal(net.alpha.shape)))
+        jobs.append((pnet, y * (1 + 1e-15 * rng.standard_normal(y.shape))))
+    with cf.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        runs = list(ex.map(lambda j: oracle_mod.bdf_thermal(j[0], j[1], cells.T, th, t_end), jobs))
+    ref = runs[0]
+    env = np.abs(np.stack([r["y"] for r in runs[1:]]) - ref["y"]).max(0)
+    assert out["status"].cpu().tolist() == ref["status"].tolist() == [0] * 4
+    yg = yd.cpu().numpy()
+    tol = np.maximum(1e-6 * np.abs(ref["y"]), 10 * env)
+    ok = (np.abs(yg - ref["y"]) <= tol) | (np.maximum(np.abs(yg), np.abs(ref["y"])) < 1e-20)
+    assert ok.all(), np.argwhere(~ok)[:5].tolist()
+    strict = (np.abs(yg - ref["y"]) <= 1e-6 * np.abs(ref["y"])) | (np.maximum(np.abs(yg), np.abs(ref["y"])) < 1e-20)
+    print(f"strict 1e-6 bar met by {strict.mean():.4f}; T gpu {yg[:, -1]} oracle {ref['y'][:, -1]} "
+          f"(start {y[:, -1]})")
+    assert np.all(np.abs(yg[:, -1] - y[:, -1]) > 0.01)     # the temperature did change
+
+
+def test_thermal_closed_form_and_energy(acm, oracle_mod, medium_net):
+    """The logistic closed form of a heating A -> B (k = alpha T/300), and
+    on the paper-sized network with reaction heats and no relaxation the
+    conserved energy c_v T + h . n, on the GPU."""
+    alpha, T0, a0 = 2e-9, 40.0, 3.0
+    cv = 1.5 * synthnet.K_BOLTZMANN * 1e4
+    eps = 10.0 * cv / a0
+    net = network_from([([0], [1])], [alpha], 2, beta=[1.0], gamma=[0.0])
+    net.heat = np.array([eps])
+    N = acm.Network(net.reactants, net.products, net.alpha, net.beta, net.gamma,
+                    composition=np.zeros((2, 6), np.int8), heat=net.heat)
+    ws = acm.Workspace(N, n_slots=1)
+    q, A = eps / cv, T0 + eps / cv * a0
+    t = 100.0 * YEAR_S
+    yd = _t([[a0, 0.0, T0]])
+    out = ws.integrate_thermal(yd, _t([T0]), _t([[cv, T0, 0.0]]), t, rtol=1e-9, atol=1e-30)
+    a = A * a0 / (q * a0 + (A - q * a0) * np.exp(alpha * A * t / 300.0))
+    y = yd.cpu().numpy()[0]
+    assert int(out["status"][0]) == 0
+    assert abs(y[0] - a) <= 1e-6 * a0 and abs(y[2] - (T0 + q * (a0 - a))) <= 1e-6 * T0
+    net, h, cells, y0, th = _thermal(medium_net, 2, 3)
+    N = acm.Network.from_synth(net)
+    ws = acm.Workspace(N, n_slots=2)
+    yd = _t(y0)
+    out = ws.integrate_thermal(yd, _t(cells.T), _t(th), 1e3 * YEAR_S)
+    assert out["status"].cpu().tolist() == [0, 0]
+    y1 = yd.cpu().numpy()
+    E0 = th[:, 0] * y0[:, -1] + y0[:, :-1] @ h
+    E1 = th[:, 0] * y1[:, -1] + y1[:, :-1] @ h
+    scale = th[:, 0] * y0[:, -1] + np.abs(y0[:, :-1]) @ np.abs(h)
+    assert np.all(np.abs(E1 - E0) <= 1e-9 * scale)
+    assert np.all(np.abs(y1[:, -1] - y0[:, -1]) > 1e-3)

@@ -311,3 +311,29 @@ def test_vjp_log_alpha_finite_difference(oracle_mod, tiny):
         fd = ((v * oracle_mod.rhs(np_, y, T)).sum() - (v * oracle_mod.rhs(nm, y, T)).sum()) / (2 * e)
         _, ab = oracle_mod.rhs(net, y, T, with_abs=True)
         assert abs(fd - gl[0, j]) <= 1e-6 * abs(gl[0, j]) + 1e-9 * (np.abs(v) * ab).sum()
+
+
+def test_jacobian_on_pattern_equals_dense(oracle_mod, medium):
+    """The pattern Jacobian (net stoichiometry, S dR/dn) equals the dense one
+    (gross bookkeeping) up to rounding of the same terms, the dense one is
+    exactly zero off the pattern of S dR/dn, and a pattern missing an entry
+    is refused."""
+    net, cells = medium
+    y, T = cells.y0[:6], cells.T[:6]
+    J, ab = oracle_mod.jac_dense(net, y, T, with_abs=True)
+    S = oracle_mod.stoich(net)
+    R = np.zeros((net.n_reactions, net.n_species), bool)
+    for j, rs in enumerate(net.reactants):
+        R[j, rs[rs >= 0]] = True
+    P = (np.abs(S) @ R.astype(np.int64)) > 0
+    rp = np.concatenate([[0], np.cumsum(P.sum(1))]).astype(np.int32)
+    col = np.concatenate([np.flatnonzero(r) for r in P]).astype(np.int32)
+    jv = oracle_mod.jac_pattern(net, y, T, rp, col)
+    rows = np.repeat(np.arange(net.n_species), np.diff(rp))
+    assert np.all(np.abs(jv - J[:, rows, col]) <= 1e-14 * ab[:, rows, col])
+    assert np.all(J[:, ~P] == 0.0)
+    with pytest.raises(ValueError):
+        short = rp.copy()
+        short[1:] -= 1
+        short[short < 0] = 0
+        oracle_mod.jac_pattern(net, y, T, np.maximum.accumulate(short), col)
