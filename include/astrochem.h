@@ -228,6 +228,21 @@ ac_status ac_vjp(const ac_net *net, const double *log_alpha, int64_t n_cells, co
                  const double *T, const double *v, double *gy, double *g_logalpha,
                  ac_stream stream);
 
+/* ac_vjp for callers that cannot allocate device memory: code recorded
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc. Same arguments and results as ac_vjp (bit for bit: same
+ * kernels, same fixed grid), but the per-workgroup partial sums of
+ * g_logalpha live in a scratch array the library holds on each GPU for the
+ * life of the process (512 rows of at most 8192 reactions, 32 MiB), not in
+ * the network's buffer. The call allocates nothing. Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (on different
+ * streams or threads) race and must be serialised by the caller.
+ * AC_ELIMIT when g_logalpha is requested for a network of more than 8192
+ * reactions. */
+ac_status ac_vjp_static(const ac_net *net, const double *log_alpha, int64_t n_cells,
+                        const double *y, const double *T, const double *v, double *gy,
+                        double *g_logalpha, ac_stream stream);
+
 /* ------------------------------------------- temperature as a state
  * Codes that solve temperature and abundances together within the stiff
  * solver (Sec. 5) make T part of the state. Per cell the state is

@@ -69,6 +69,7 @@ def _load() -> C.CDLL:
         "ac_jac": [vp, vp, i64, vp, vp, vp, vp],
         "ac_rhs_jac": [vp, vp, i64, vp, vp, vp, vp, vp],
         "ac_vjp": [vp, vp, i64, vp, vp, vp, vp, vp, vp],
+        "ac_vjp_static": [vp, vp, i64, vp, vp, vp, vp, vp, vp],
         "ac_rhs_thermal": [vp, vp, i64, vp, vp, vp, vp, vp],
         "ac_jac_thermal": [vp, vp, i64, vp, vp, vp, vp, vp],
     }
@@ -361,6 +362,21 @@ def ac_jac_thermal(net: Network, log_alpha, y, T, therm, jvals, stream=None):
         _check_dev(log_alpha, (net.n_reactions,), "log_alpha")
     check(lib.ac_jac_thermal(net.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T), _ptr(therm),
                              _ptr(jvals), _stream(stream)), "ac_jac_thermal")
+
+
+def ac_vjp_static(net: Network, log_alpha, y, T, v, gy, g_logalpha, stream=None):
+    """ac_vjp with its partial sums in the library's per-GPU scratch array:
+    allocates nothing (for graph capture and serving loops)."""
+    n = _cells(net, y, T)
+    _check_dev(v, (n, net.n_species), "v")
+    if gy is not None:
+        _check_dev(gy, (n, net.n_species), "gy")
+    if g_logalpha is not None:
+        _check_dev(g_logalpha, (net.n_reactions,), "g_logalpha")
+    if log_alpha is not None:
+        _check_dev(log_alpha, (net.n_reactions,), "log_alpha")
+    check(lib.ac_vjp_static(net.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T), _ptr(v), _ptr(gy),
+                            _ptr(g_logalpha), _stream(stream)), "ac_vjp_static")
 
 
 def ac_sparse_format(dense, fmt: int, width: int = 0):

@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "netbuild.cpp", "kernels_chem.hip", "kernels_bdf.hip", "kernels_adj.hip",
-           "kernels_thermal.hip"]
+           "static_scratch.hip", "kernels_thermal.hip"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -420,6 +420,25 @@ ac_status ac_vjp(const ac_net *net, const double *log_alpha, int64_t n_cells, co
   return e == hipSuccess ? AC_OK : hip_fail(e, "ac_vjp launch");
 }
 
+ac_status ac_vjp_static(const ac_net *net, const double *log_alpha, int64_t n_cells,
+                        const double *y, const double *T, const double *v, double *gy,
+                        double *g_logalpha, ac_stream stream) {
+  if (ac_status s = check_cells(net, n_cells)) return s;
+  if (n_cells && (!y || !T || !v)) return fail(AC_EINVAL, "null y, T or v");
+  double *part = nullptr;
+  if (g_logalpha) {
+    if (net->d.nr > ac::VJP_STATIC_NR)
+      return fail(AC_ELIMIT, "ac_vjp_static: the library's scratch holds partial sums of at most " +
+                                 std::to_string(ac::VJP_STATIC_NR) + " reactions");
+    hipError_t e = ac::vjp_static_scratch(&part);
+    if (e != hipSuccess) return hip_fail(e, "ac_vjp_static scratch lookup");
+  }
+  static_assert(ac::VJP_STATIC_ROWS == VJP_ROWS, "same fixed grid as ac_vjp");
+  hipError_t e = ac::launch_vjp(net->d, log_alpha, n_cells, y, T, v, gy, g_logalpha, part,
+                                ac::VJP_STATIC_ROWS, hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_vjp_static launch");
+}
+
 static ac_status thermal_args(const ac_net *net, int64_t n_cells, const double *y,
                               const double *T, const double *therm) {
   if (ac_status s = check_cells(net, n_cells)) return s;

@@ -63,4 +63,12 @@ hipError_t launch_jac_thermal(const DNet &n, const double *la, int64_t n_cells, 
                               const double *cond, const double *therm, double *jvals,
                               hipStream_t stream);
 
+// Allocation-free VJP: partial-sum rows held in a device array of the
+// library (static_scratch.hip), VJP_STATIC_ROWS rows of at most
+// VJP_STATIC_NR reactions. *ptr gets this device's copy (looked up on the
+// first call on each device).
+constexpr int VJP_STATIC_ROWS = 512;
+constexpr int VJP_STATIC_NR = 8192;
+hipError_t vjp_static_scratch(double **ptr);
+
 }  // namespace ac
