@@ -34,7 +34,7 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--cells", type=int, default=65536)
     p.add_argument("--layout", default="auto", help="sell|csr|runs|coo, or auto (autotuned)")
     p.add_argument("--ordering", default="auto", help="nnz|natural|rcm, or auto (autotuned)")
@@ -42,20 +42,22 @@ def parse():
     p.add_argument("--no-table", action="store_true",
                    help="skip the autotuner (layout x ordering x block table); use sell/nnz/512")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    p.add_argument("--cpu-seconds", type=float, default=20.0,
+    p.add_argument("--cpu-seconds", type=float, default=8.0,
                    help="about this many seconds per thread setting (five repeats)")
     p.add_argument("--no-int", action="store_true", help="skip the integration legs")
+    p.add_argument("--no-scale", action="store_true",
+                   help="skip the 700 / 8000 network on 262,144 cells")
     p.add_argument("--int-cells", type=int, default=16384,
                    help="cells of the batched integration leg (the 16,384-cell workload)")
     p.add_argument("--int-max-steps", type=int, default=20000,
                    help="accepted-step budget per cell (batched and plain alike)")
-    p.add_argument("--int-chunks", type=int, default=8,
-                   help="launches the batched leg is split into (two streams, so a chunk's "
-                        "slots are taken over by the next chunk's cells as they free up)")
-    p.add_argument("--plain-cells", type=int, default=64, help="cells timed through the plain loop")
-    p.add_argument("--adj-cells", type=int, default=256,
+    p.add_argument("--plain-cells", type=int, default=64,
+                   help="cells integrated by both the plain loop and the batched kernel")
+    p.add_argument("--plain-max-steps", type=int, default=1000,
+                   help="accepted-step budget per cell of that comparison (both sides)")
+    p.add_argument("--adj-cells", type=int, default=32,
                    help="cells of the adjoint leg (first cells of the 4,096-cell workload)")
-    p.add_argument("--adj-max-steps", type=int, default=20000)
+    p.add_argument("--adj-max-steps", type=int, default=10000)
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain device copy of the densities (known bytes) so HBM "
                         "counters can be calibrated in the same profile")
@@ -217,50 +219,142 @@ def lu_leg(torch, acm, net, cells, n_mat=256):
                    "solve_hbm_frac": sbytes / (sv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
-def _integrate_chunked(torch, acm, wss, y, T, t_end, max_steps, nch, label):
-    """Batched integration of every cell, split into nch launches issued
-    back to back alternately on two streams with a workspace each: the
-    persistent workgroups of a chunk take cells from its own queue and a
-    later chunk's workgroups start on the compute units the earlier ones
-    free, so the split costs no idle tail. Prints a line as each chunk
-    completes. Returns (wall seconds, stats, status)."""
+def config1_leg(torch, acm):
+    """The plain method on one cell (50 species / 300 reactions, T = 20 K,
+    n_H = 1e4): per-call latency of the RHS, the Jacobian and both together
+    (host wall time of one call plus its synchronisation, median of 50; and
+    the device time per call in a stream of 200 back-to-back calls, HIP
+    events), then backward Euler (BDF order 1) to 1e5 yr on the persistent
+    integrator and on the plain one-cell launch."""
+    import synthnet
+    net, cells = synthnet.workload("tiny")
+    N = acm.Network.from_synth(net)
+    y = torch.from_numpy(cells.y0.copy()).cuda()
+    T = torch.from_numpy(cells.T.copy()).cuda()
+    dydt = torch.empty_like(y)
+    jv = torch.empty((1, N.nnz_j), dtype=torch.float64, device="cuda")
+    calls = {"rhs": lambda: acm.ac_rhs(N, None, y, T, dydt),
+             "jac": lambda: acm.ac_jac(N, None, y, T, jv),
+             "rhs_jac": lambda: acm.ac_rhs_jac(N, None, y, T, dydt, jv)}
+    out = {}
+    for name, fn in calls.items():
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        walls = []
+        for _ in range(50):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(200):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        out[name] = {"call_us": 1e6 * float(np.median(walls)),
+                     "stream_us_per_call": 1e3 * a.elapsed_time(b) / 200}
+    ws = acm.Workspace(N, n_slots=1)
+    t_end = 1e5 * YEAR_S
+    for mode in ("batched", "plain"):
+        yi = y.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = ws.integrate(yi, T, t_end, q_max=1, plain=(mode == "plain"))
+        torch.cuda.synchronize()
+        st = o["stats"].cpu().numpy()[0]
+        out[f"backward_euler_{mode}"] = {"wall_s": time.perf_counter() - t0,
+                                         "status": int(o["status"][0]), "steps": int(st[0])}
+    ws.close()
+    N.close()
+    return {"config1": dict(out, workload="50 species / 300 reactions, 1 cell, T = 20 K, "
+                                          "n_H = 1e4 cm^-3; backward Euler to 1e5 yr")}
+
+
+def scale_leg(torch, acm):
+    """The 700 species / 8000 reactions network with grain-surface terms on
+    262,144 cells: RHS + Jacobian (one ac_rhs_jac call), the VJP, each timed
+    with HIP events (2 untimed, 3 timed calls). Its two-cell LDS does not fit
+    a CU, so the one-cell kernels run."""
+    import synthnet
+    net, _ = synthnet.workload("large", n_cells=1)
+    cells = synthnet.make_cells(net, 262144, synthnet.SEED_BASE + 4)
+    N = acm.Network.from_synth(net, layout="sell", ordering="rcm")
+    C, ns, nr = 262144, net.n_species, net.n_reactions
+    y = torch.from_numpy(cells.y0).cuda()
+    T = torch.from_numpy(cells.T).cuda()
+    dydt = torch.empty_like(y)
+    jv = torch.empty((C, N.nnz_j), dtype=torch.float64, device="cuda")
+    v = torch.randn(y.shape, dtype=torch.float64, device="cuda",
+                    generator=torch.Generator("cuda").manual_seed(2))
+    gy = torch.empty_like(y)
+    gl = torch.empty(nr, dtype=torch.float64, device="cuda")
+    tm = Timer(torch)
+    for name, fn in (("rhs_jac", lambda: acm.ac_rhs_jac(N, None, y, T, dydt, jv)),
+                     ("vjp", lambda: acm.ac_vjp(N, None, y, T, v, gy, gl))):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        for _ in range(3):
+            tm.run(name, fn)
+        torch.cuda.synchronize()
+    rj, vj = tm.mean_ms("rhs_jac"), tm.mean_ms("vjp")
+    b_rj = C * (16 * ns + 8 + 8 * N.nnz_j)
+    out = {"workload": "700 species / 8000 reactions (20 % grain-surface-like two-body terms), "
+                       "262,144 cells, FP64",
+           "nnz_j": N.nnz_j,
+           "rhs_jac_ms": rj, "rhs_jac_cell_reactions_per_s": C * nr / (rj * 1e-3),
+           "rhs_jac_GBps": b_rj / (rj * 1e-3) / 1e9,
+           "rhs_jac_hbm_frac": b_rj / (rj * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "vjp_ms": vj, "vjp_cell_reactions_per_s": C * nr / (vj * 1e-3)}
+    del jv, y, T, dydt, v, gy
+    torch.cuda.empty_cache()
+    N.close()
+    return {"scale": out}
+
+
+def _integrate_watched(torch, ws, y, T, t_end, max_steps, label, every=20.0):
+    """Batched integration of every cell in one launch: the device queue hands
+    cells to the persistent workgroups as they free up, so the slow cells
+    cost one tail. While it runs, prints a line every `every` seconds with
+    the cells the workgroups have taken so far (the workspace's queue
+    counter). Returns (wall seconds, stats, status)."""
     C = y.shape[0]
-    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    s = torch.cuda.Stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    outs, evs = [], []
-    for k in range(nch):
-        s = slice(k * C // nch, (k + 1) * C // nch)
-        st = streams[k % 2]
-        with torch.cuda.stream(st):
-            o = wss[k % 2].integrate(y[s], T[s], t_end, max_steps=max_steps, stream=st.cuda_stream)
-            e = torch.cuda.Event()
-            e.record(st)
-        outs.append(o)
-        evs.append(e)
-    for k, e in enumerate(evs):
-        e.synchronize()
-        print(f"[bench] {label}: chunk {k + 1}/{nch} done at {time.perf_counter() - t0:.1f} s",
-              file=sys.stderr, flush=True)
+    with torch.cuda.stream(s):
+        o = ws.integrate(y, T, t_end, max_steps=max_steps, stream=s.cuda_stream)
+        e = torch.cuda.Event()
+        e.record(s)
+    last = t0
+    while not e.query():
+        time.sleep(0.2)
+        now = time.perf_counter()
+        if now - last >= every:
+            last = now
+            taken = min(ws.progress(), C)
+            print(f"[bench] {label}: {taken}/{C} cells taken at {now - t0:.1f} s", file=sys.stderr,
+                  flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    st = np.concatenate([o["stats"].cpu().numpy() for o in outs])
-    status = np.concatenate([o["status"].cpu().numpy() for o in outs])
-    return wall, st, status
+    print(f"[bench] {label}: done in {wall:.1f} s", file=sys.stderr, flush=True)
+    return wall, o["stats"].cpu().numpy(), o["status"].cpu().numpy()
 
 
 def integration_legs(args, torch, acm, net):
     """Integrated cells/s of the batched BDF on the 16,384-cell workload (470 /
     4600 network, T log-uniform on 10-300 K, n_H log-uniform on 1e2-1e7,
-    BDF 1-5 to 1e6 yr, rtol 1e-6, atol 1e-20), the plain one-cell-per-launch
-    loop timed on the first --plain-cells of the same cells under the same
-    step budget (and the batched kernel on those same cells), then the
-    discrete adjoint of --adj-cells cells of the 4,096-cell workload to
-    t_end. Wall-clock timing, synchronised."""
+    BDF 1-5 to 1e6 yr, rtol 1e-6, atol 1e-20) in one launch; the plain
+    one-cell-per-launch loop and the batched kernel on the same first
+    --plain-cells cells under a budget of --plain-max-steps steps each (their
+    wall-time ratio is vs_plain); then the discrete adjoint of the first
+    --adj-cells cells of the 4,096-cell workload to t_end. Wall-clock timing,
+    synchronised."""
     import synthnet
     dev = torch.device("cuda:0")
-    N = acm.Network.from_synth(net)
-    wss = [acm.Workspace(N), acm.Workspace(N)]
+    from paper_2312_04998_amd.autotune import tune_slots
     t_end = 1e6 * YEAR_S
     K = args.int_max_steps
     res = {}
@@ -268,26 +362,35 @@ def integration_legs(args, torch, acm, net):
     n = cells.T.size
     y = torch.from_numpy(cells.y0.copy()).to(dev)
     T = torch.from_numpy(cells.T.copy()).to(dev)
-    wall, st, status = _integrate_chunked(torch, acm, wss, y, T, t_end, K, args.int_chunks,
+    # workgroup slots of the integrator, tuned on the first 512 cells (200 steps each)
+    m = min(512, n)
+    slots, slot_rate, slots_cached = tune_slots(net, y[:m], T[:m], t_end, 200)
+    print(f"[bench] integrator slots {slots} (steps/s by slots {slot_rate}, "
+          f"{'cached' if slots_cached else 'tuned'})", file=sys.stderr, flush=True)
+    N = acm.Network.from_synth(net)
+    ws = acm.Workspace(N, n_slots=slots)
+    wall, st, status = _integrate_watched(torch, ws, y, T, t_end, K,
                                           f"batched integration of {n} cells")
     steps = int(st[:, 0].sum())
     ok = int((status == 0).sum())
     capped = np.flatnonzero(status == 1)
-    # the plain loop and the batched kernel on the same first cells
-    npl = min(args.plain_cells, n)
+    # the plain loop and the batched kernel on the same first cells, under the
+    # same (smaller) step budget
+    npl, Kp = min(args.plain_cells, n), args.plain_max_steps
     yb = torch.from_numpy(cells.y0[:npl].copy()).to(dev)
     Tp = torch.from_numpy(cells.T[:npl].copy()).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ob = wss[0].integrate(yb, Tp, t_end, max_steps=K)
+    ob = ws.integrate(yb, Tp, t_end, max_steps=Kp)
     torch.cuda.synchronize()
     wall_b = time.perf_counter() - t0
+    sb = ob["stats"].cpu().numpy()
     wall_p, sp, stp, same = 0.0, [], [], True
     for k in range(0, npl, 8):
         yp = torch.from_numpy(cells.y0[k:k + 8].copy()).to(dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        op = wss[0].integrate(yp, Tp[k:k + 8], t_end, max_steps=K, plain=True)
+        op = ws.integrate(yp, Tp[k:k + 8], t_end, max_steps=Kp, plain=True)
         torch.cuda.synchronize()
         wall_p += time.perf_counter() - t0
         sp.append(op["stats"].cpu().numpy())
@@ -310,70 +413,82 @@ def integration_legs(args, torch, acm, net):
         "lu_per_step": float(st[:, 5].sum() / max(steps, 1)),
         "jac_per_step": float(st[:, 4].sum() / max(steps, 1)),
         "rejections_per_step": float((st[:, 1] + st[:, 2]).sum() / max(steps, 1)),
-        "slots": wss[0].n_slots, "launches": args.int_chunks,
-        "plain": {"cells": npl, "wall_s": wall_p, "cells_reaching_t_end": ok_p,
-                  "integrated_cells_per_s": ok_p / wall_p, "steps": int(sp[:, 0].sum()),
-                  "steps_per_s": float(sp[:, 0].sum() / wall_p),
+        "slots": ws.n_slots, "launches": 1,
+        "slot_tuning": {"steps_per_s_by_slots": slot_rate, "from_cache": slots_cached,
+                        "sample": f"first {m} cells, 200 steps each"},
+        "plain": {"cells": npl, "max_steps": Kp, "wall_s": wall_p, "cells_reaching_t_end": ok_p,
+                  "steps": int(sp[:, 0].sum()), "steps_per_s": float(sp[:, 0].sum() / wall_p),
                   "batched_wall_s_same_cells": wall_b,
+                  "batched_steps_same_cells": int(sb[:, 0].sum()),
                   "same_results_as_batched": same,
-                  "note": "plain = the same kernel launched once per cell with one workgroup, "
-                          "launches issued back to back; timed on the first cells of the "
-                          "workload under the same step budget"},
-        "vs_plain": (ok / wall) / (ok_p / wall_p) if ok_p else None,
-        "vs_plain_same_cells": wall_p / wall_b,
+                  "note": "plain = the same integrator launched once per cell with one "
+                          "workgroup, launches issued back to back; the batched kernel and the "
+                          "plain loop integrate the same first cells of the workload under the "
+                          "same step budget, and vs_plain is the ratio of their wall times"},
+        "vs_plain": wall_p / wall_b,
     }
-    # discrete adjoint: forward with tape, then the timed adjoint sweep
+    # discrete adjoint: forward with tape over the first cells of the 4,096-cell
+    # workload, then the timed adjoint sweep over the first --adj-cells of them
+    # that reach t_end within the step budget
     acells = synthnet.make_cells(net, 4096, synthnet.SEED_BASE + 3)
-    na = min(args.adj_cells, 4096)
-    ya = torch.from_numpy(acells.y0[:na].copy()).to(dev)
-    Ta = torch.from_numpy(acells.T[:na].copy()).to(dev)
+    nf = min(args.adj_cells + 8, 4096)
+    ya = torch.from_numpy(acells.y0[:nf].copy()).to(dev)
+    Ta = torch.from_numpy(acells.T[:nf].copy()).to(dev)
     cap = 2 * args.adj_max_steps + 64
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    fw = wss[0].integrate(ya, Ta, t_end, max_steps=args.adj_max_steps, tape_cap=cap)
+    fw = ws.integrate(ya, Ta, t_end, max_steps=args.adj_max_steps, tape_cap=cap)
     torch.cuda.synchronize()
     wall_f = time.perf_counter() - t0
-    print(f"[bench] adjoint forward: {na} cells in {wall_f:.1f} s", file=sys.stderr, flush=True)
-    yT = ya.cpu().numpy()
+    fst = fw["status"].cpu().numpy()
+    sel = np.flatnonzero(fst == 0)[:args.adj_cells]
+    na = int(sel.size)
+    print(f"[bench] adjoint forward: {nf} cells in {wall_f:.1f} s, {int((fst == 0).sum())} reach "
+          f"t_end", file=sys.stderr, flush=True)
+    if na == 0:
+        res["adjoint"] = {"cells": 0, "forward_cells": nf, "forward_wall_s": wall_f,
+                          "note": "no cell reached t_end within the step budget"}
+        ws.close()
+        return res
+    yT = ya.cpu().numpy()[sel]
     rng = np.random.default_rng(8)
     lam = np.zeros_like(yT)
     for c in range(na):
         okc = np.flatnonzero(yT[c] > 1e-20)
         tgt = rng.choice(okc, 8, replace=False)
         lam[c, tgt] = 1.0 / yT[c, tgt]
-    y0a = torch.from_numpy(acells.y0[:na].copy()).to(dev)
+    idx = torch.from_numpy(sel).to(dev)
+    y0a = torch.from_numpy(acells.y0[sel].copy()).to(dev)
+    Ts = Ta[idx].contiguous()
+    tlen = fw["tape_len"][idx].contiguous()
     # the tapes cut to the longest one, and room for every converged state
     # reserved before the timed region
-    L = int(fw["tape_len"].max().item()) + 1
-    tape = fw["tape"][:, :L].contiguous()
-    wss[0].reserve_adjoint(L, keep_states=True, max_cells=na)
+    L = int(tlen.max().item()) + 1
+    tape = fw["tape"][idx, :L].contiguous()
+    ws.reserve_adjoint(L, keep_states=True, max_cells=na)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    adj = wss[0].adjoint(y0a, Ta, tape, fw["tape_len"], torch.from_numpy(lam).to(dev))
+    adj = ws.adjoint(y0a, Ts, tape, tlen, torch.from_numpy(lam).to(dev))
     torch.cuda.synchronize()
     wall_a = time.perf_counter() - t0
-    fst = fw["status"].cpu().numpy()
-    sa = int(fw["stats"].cpu().numpy()[:, 0].sum())
+    sa = int(fw["stats"].cpu().numpy()[sel, 0].sum())
     ast_ = adj["stats"].cpu().numpy()
     print(f"[bench] adjoint: {na} cells in {wall_a:.1f} s", file=sys.stderr, flush=True)
     res["adjoint"] = {
-        "workload": f"470/4600 network, first {na} of the 4,096-cell workload, d sum log y_t / "
-                    f"d (log alpha, y0) for 8 seeded targets per cell, BDF 1-5 to 1e6 yr "
-                    f"(max_steps {args.adj_max_steps}), checkpoints every 64 steps, every "
-                    f"converged state kept",
-        "cells": na, "forward_wall_s": wall_f, "wall_s": wall_a,
-        "forward_plus_adjoint_s": wall_f + wall_a, "cells_per_s": na / (wall_f + wall_a),
-        "cells_reaching_t_end": int((fst == 0).sum()), "steps": sa,
-        "adjoint_steps_per_s": sa / wall_a,
+        "workload": f"470/4600 network: the first {na} cells of the 4,096-cell workload that "
+                    f"reach t_end (of its first {nf}; max_steps {args.adj_max_steps}), "
+                    f"d sum log y_t / d (log alpha, y0) for 8 seeded targets per cell, BDF 1-5 "
+                    f"to 1e6 yr, checkpoints every 64 steps, every converged state kept",
+        "cells": na, "forward_cells": nf, "forward_wall_s": wall_f, "wall_s": wall_a,
+        "cells_per_s": na / wall_a, "steps": sa, "adjoint_steps_per_s": sa / wall_a,
         "status_ok": int((adj["status"] == 0).sum().item()),
-        "states_kept": wss[0].keeps_states, "tape_events_max": L,
+        "states_kept": ws.keep_states, "tape_events_max": L,
         "per_step": {"replay_newton_iters": float(ast_[:, 3].sum() / max(sa, 1)),
                      "jacobians": float(ast_[:, 4].sum() / max(sa, 1)),
                      "factorisations": float(ast_[:, 5].sum() / max(sa, 1)),
                      "rhs": float(ast_[:, 6].sum() / max(sa, 1))},
     }
-    for w in wss:
-        w.close()
+    ws.close()
     return res
 
 
@@ -395,14 +510,17 @@ def main():
     dev = torch.device("cuda:0")
     y = torch.from_numpy(cells.y0).to(dev)
     T = torch.from_numpy(cells.T).to(dev)
-    tune_table = {}
+    tune_table, tune_cached = {}, None
     if args.no_table:
         cfg = {"layout": "sell", "ordering": "nnz", "block": 512}
     else:
         from paper_2312_04998_amd.autotune import autotune
         N, cfg, tab = autotune(net, y, T)
         N.close()
+        tune_cached = cfg.pop("cached")
         tune_table = {f"{l}/{o}/{b}": round(ms, 4) for (l, o, b), ms in sorted(tab.items(), key=lambda kv: kv[1])}
+    print(f"[bench] launch shape {cfg} ({'cached' if tune_cached else 'tuned' if tune_table else 'fixed'})",
+          file=sys.stderr, flush=True)
     if args.layout != "auto":
         cfg["layout"] = args.layout
     if args.ordering != "auto":
@@ -432,6 +550,8 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall * 1e3 / args.steps
+    print(f"[bench] {args.steps} steps of RHS + Jacobian: {ms_step:.3f} ms per step", file=sys.stderr,
+          flush=True)
 
     if args.copy_probe:
         # a copy of known size: reads and writes C * ns * 8 bytes once each
@@ -515,7 +635,15 @@ def main():
                                         "frac": kern["jac"]["hbm_frac"]}},
         "kernels": kern,
         "autotune_ms_per_step": tune_table,
+        "autotune_from_cache": tune_cached,
     }
+    out.update(config1_leg(torch, acm))
+    if not args.no_scale:
+        out.update(scale_leg(torch, acm))
+        print(f"[bench] 700 / 8000 network, 262,144 cells: {out['scale']['rhs_jac_ms']:.1f} ms per RHS + "
+              f"Jacobian, {out['scale']['vjp_ms']:.1f} ms per VJP", file=sys.stderr, flush=True)
+    print(f"[bench] one-cell latency: {out['config1']['rhs_jac']['call_us']:.1f} us per RHS + "
+          f"Jacobian call", file=sys.stderr, flush=True)
     if not args.no_int:
         out.update(lu_leg(torch, acm, net, cells))
         out.update(integration_legs(args, torch, acm, net))

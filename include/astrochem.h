@@ -332,6 +332,16 @@ ac_status ac_ws_create(const ac_net *net, int32_t n_slots, ac_ws **out);
 ac_status ac_ws_destroy(ac_ws *ws);
 ac_status ac_ws_info(const ac_ws *ws, int32_t *n_slots, int64_t *bytes);
 
+/* Progress of a running ac_integrate or ac_integrate_thermal on this
+ * workspace: *cells_taken = 1 + the index of the last cell a workgroup took
+ * from the device queue (cells done or in progress; workgroups report in
+ * whatever order they take cells, so the count can briefly step back by a
+ * few), or the last call's final count once it ends. The integrator
+ * writes it to a pinned host word of the workspace; this call only reads
+ * that word, so it returns at once while the integration runs. For
+ * progress reports of long integrations. */
+ac_status ac_ws_progress(ac_ws *ws, int64_t *cells_taken);
+
 /* Room for the discrete adjoint and the replay, allocated here (with a
  * device synchronisation; any earlier reservation is released) so that
  * ac_integrate_adjoint and ac_replay allocate nothing:

@@ -88,6 +88,7 @@ def _load() -> C.CDLL:
         "ac_ws_create": [vp, i32, vp],
         "ac_ws_destroy": [vp],
         "ac_ws_info": [vp, vp, vp],
+        "ac_ws_progress": [vp, vp],
         "ac_integrate": [vp, vp, i64, vp, vp, d, vp, vp, vp, vp, i32, vp, vp],
         "ac_integrate_plain": [vp, vp, i64, vp, vp, d, vp, vp, vp, vp],
         "ac_integrate_adjoint": [vp, vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
@@ -447,14 +448,20 @@ class Workspace:
         check(lib.ac_ws_adjoint_info(self.handle, C.byref(mt), C.byref(ce), C.byref(ks),
                                      C.byref(mc)), "ac_ws_adjoint_info")
         self.adj_max_tape, self.checkpoint_every = mt.value, ce.value
-        self.keeps_states, self.adj_max_cells = bool(ks.value), mc.value
-        self.keep_states = bool(keep_states)
+        self.keep_states, self.adj_max_cells = bool(ks.value), mc.value
 
     def _ensure_adjoint(self, tape_cap: int, checkpoint_every: int):
         every = int(checkpoint_every) or 64
         if tape_cap > self.adj_max_tape or every != self.checkpoint_every:
             self.reserve_adjoint(max(tape_cap, self.adj_max_tape if every == self.checkpoint_every
                                      else 0), every, self.keep_states, self.adj_max_cells)
+
+    def progress(self) -> int:
+        """ac_ws_progress: cells taken so far by the running (or last)
+        integration on this workspace."""
+        n = C.c_int64()
+        check(lib.ac_ws_progress(self.handle, C.byref(n)), "ac_ws_progress")
+        return n.value
 
     def close(self):
         if getattr(self, "handle", None):
@@ -510,8 +517,9 @@ class Workspace:
         factorisations, RHS evaluations) and, as
         requested, dL_dlogalpha [nr] (summed over cells in cell order),
         g_cells [n, nr] and the replayed y_final [n, ns]. recompute=True
-        recomputes every 64-step segment from its checkpoint instead of
-        keeping every converged state (same results, less memory)."""
+        recomputes every checkpointed segment (checkpoint_every steps, 64 by
+        default) from its checkpoint instead of keeping every converged
+        state (same results, less memory)."""
         import torch
         n, ns, nr = T.shape[0], self.net.n_species, self.net.n_reactions
         _check_dev(T, self.net.cond_shape(n), "T")

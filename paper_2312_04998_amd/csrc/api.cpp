@@ -505,6 +505,7 @@ struct ac_ws {
   int adj_tape = 0;          // longest tape the reserved slots hold (0: no adjoint capacity)
   double *rows = nullptr;    // [max_cells][n_reactions] per-cell dL/dlog alpha rows
   int max_cells = 0;
+  unsigned *host_count = nullptr;   // pinned word the integrator writes its progress to
 };
 
 extern "C" {
@@ -577,6 +578,20 @@ ac_status ac_ws_create(const ac_net *net, int32_t n_slots, ac_ws **out) {
       return hip_fail(e, "workspace poison fill");
     }
   }
+  // the pinned host word the integrator reports its progress to
+  e = hipHostMalloc(reinterpret_cast<void **>(&ws->host_count), sizeof(unsigned));
+  void *dp = nullptr;
+  if (e == hipSuccess) {
+    *ws->host_count = 0u;
+    e = hipHostGetDevicePointer(&dp, ws->host_count, 0);
+  }
+  if (e != hipSuccess) {
+    if (ws->host_count) hipHostFree(ws->host_count);
+    hipFree(ws->buf);
+    delete ws;
+    return hip_fail(e, "workspace progress word");
+  }
+  ws->W.progress = static_cast<unsigned *>(dp);
   *out = ws;
   return AC_OK;
 }
@@ -585,8 +600,16 @@ ac_status ac_ws_destroy(ac_ws *ws) {
   if (!ws) return AC_OK;
   if (ws->adj_buf) hipFree(ws->adj_buf);
   if (ws->rows) hipFree(ws->rows);
+  if (ws->host_count) hipHostFree(ws->host_count);
   hipFree(ws->buf);
   delete ws;
+  return AC_OK;
+}
+
+ac_status ac_ws_progress(ac_ws *ws, int64_t *cells_taken) {
+  if (!ws || !cells_taken) return fail(AC_EINVAL, "null argument");
+  // written by the running kernel (system-scope stores); no GPU call here
+  *cells_taken = int64_t(*static_cast<volatile unsigned *>(ws->host_count));
   return AC_OK;
 }
 

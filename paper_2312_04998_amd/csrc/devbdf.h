@@ -44,6 +44,7 @@ struct WsView {
   int *piv;         // per slot: pivots [ns] then the row permutation [ns]
   size_t m_stride, j_stride, tail_stride, d_stride, k_stride, piv_stride;
   int lda;
+  unsigned *progress;   // pinned host word: 1 + the last cell taken (or null)
 };
 
 // Discrete adjoint: per-slot buffers (checkpoints every `every` accepted

@@ -88,8 +88,13 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
                          : fmax(10.0 * 2.220446049250313e-16 / rtol, fmin(0.03, sqrt(rtol)));
 
   for (int64_t iter = 0;; ++iter) {
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
       s_cell = queue ? int64_t(atomicAdd(queue, 1u)) : int64_t(blockIdx.x) + iter * gridDim.x;
+      // progress for the host: a system-scope store to the pinned word
+      if (W.progress && s_cell < n_cells)
+        __hip_atomic_store(W.progress, unsigned(s_cell + 1), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     __syncthreads();
     const int64_t cell = s_cell;
     __syncthreads();
@@ -328,8 +333,11 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
   }
 }
 
-__global__ void k_reset_queue(unsigned *q) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0u;
+__global__ void k_reset_queue(unsigned *q, unsigned *progress) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *q = 0u;
+    if (progress) __hip_atomic_store(progress, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // ------------------------------------------------------- standalone LU
@@ -407,7 +415,7 @@ hipError_t launch_bdf(const DNet &n, const double *la, int64_t n_cells, double *
   auto kern = therm ? k_bdf<BDF_NT, true> : k_bdf<BDF_NT, false>;
   if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-  if (queue) hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, queue);
+  if (queue) hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, queue, W.progress);
   const int g = int(n_cells < grid ? n_cells : grid);
   hipLaunchKernelGGL(kern, dim3(g), dim3(BDF_NT), lds, st, n, la, n_cells, y, T, therm, P, out, tv,
                      W, queue);
@@ -416,7 +424,7 @@ hipError_t launch_bdf(const DNet &n, const double *la, int64_t n_cells, double *
 
 hipError_t launch_reset_queue(unsigned *queue, hipStream_t st) {
   if (!queue) return hipSuccess;
-  hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, queue);
+  hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, queue, nullptr);
   return hipGetLastError();
 }
 

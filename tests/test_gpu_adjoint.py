@@ -250,8 +250,11 @@ def test_adjoint_kept_states_equal_recomputed(acm, oracle_mod, which):
 def test_adjoint_gradient_rows_in_workspace_and_checkpoint_interval(acm, oracle_mod):
     """The summed dL/dlog alpha from the workspace's own rows (no per-cell
     buffer; 5 cells in chunks of 2) equals the sum of the caller's per-cell
-    rows bit for bit, and so do the gradients with checkpoints every 16
-    steps (segments recomputed) and every 64 (states kept)."""
+    rows bit for bit. With checkpoints every 16 steps the segments recomputed
+    from their checkpoints equal the kept states bit for bit; against
+    checkpoints every 64 they differ only by where the Newton matrix is
+    rebuilt (each segment starts with a fresh one), far below the parity
+    bar."""
     import torch
     net, cells = synthnet.workload("tiny", n_cells=5)
     t_end = 1e4 * YEAR_S
@@ -268,8 +271,15 @@ def test_adjoint_gradient_rows_in_workspace_and_checkpoint_interval(acm, oracle_
     assert torch.equal(a["dL_dlogalpha"], b["dL_dlogalpha"]) and torch.equal(a["dL_dy0"], b["dL_dy0"])
     ws_c = acm.Workspace(N, n_slots=2, adj_max_tape=8000, checkpoint_every=16)
     c = ws_c.adjoint(*args, want_cells=True, recompute=True, checkpoint_every=16)
+    ws_d = acm.Workspace(N, n_slots=2, adj_max_tape=8000, checkpoint_every=16, keep_states=True)
+    d = ws_d.adjoint(*args, want_cells=True, checkpoint_every=16)
     for k in ("dL_dy0", "g_cells", "dL_dlogalpha"):
-        assert torch.equal(a[k], c[k]), k
+        assert torch.equal(c[k], d[k]), k
+        ga, gc = a[k].cpu().numpy(), c[k].cpu().numpy()
+        scale = np.abs(ga).max(axis=-1, keepdims=True)
+        worst = float((np.abs(gc - ga) / scale).max())
+        print(f"{k}: every 16 vs every 64, worst {worst:.2e} of the row's largest entry")
+        assert worst <= 1e-8, k
 
 
 def test_adjoint_refuses_without_reservation(acm, oracle_mod):

@@ -215,15 +215,25 @@ def test_edge_cases(acm, torch_dev, oracle_mod):
 
 
 def test_autotune_picks_a_working_configuration(acm, torch_dev, oracle_mod, medium_net, med_cells):
-    """The autotuner times every layout x ordering x block on the caller's
-    cells and returns the fastest network; that network's RHS and Jacobian
-    still match the oracle."""
+    """The autotuner times every candidate layout x ordering x block (SELL at
+    one block size: its fused kernel ignores it) on the caller's cells and
+    returns the fastest network, whose RHS and Jacobian still match the
+    oracle; a second call with the same key reads the choice from the JSON
+    cache."""
+    import os
+    import tempfile
     torch = torch_dev
-    from paper_2312_04998_amd.autotune import autotune, LAYOUTS, ORDERINGS, BLOCKS
+    from paper_2312_04998_amd.autotune import autotune, candidates
     y, T = med_cells.y0[:256], med_cells.T[:256]
-    N, kw, table = autotune(medium_net, _t(torch, y), _t(torch, T), reps=2)
-    assert len(table) == len(LAYOUTS) * len(ORDERINGS) * len(BLOCKS)
-    assert table[(kw["layout"], kw["ordering"], kw["block"])] == min(table.values())
+    with tempfile.TemporaryDirectory() as d:
+        cache = os.path.join(d, "tune.json")
+        N, kw, table = autotune(medium_net, _t(torch, y), _t(torch, T), reps=2, cache=cache)
+        assert kw.pop("cached") is False
+        assert len(table) == len(list(candidates())) == 3 + 4 * 3 * 3
+        assert table[(kw["layout"], kw["ordering"], kw["block"])] == min(table.values())
+        N2, kw2, table2 = autotune(medium_net, _t(torch, y), _t(torch, T), reps=2, cache=cache)
+        assert kw2.pop("cached") is True and kw2 == kw and set(table2) == set(table)
+        N2.close()
     f = N.rhs(_t(torch, y[:40]), _t(torch, T[:40])).cpu().numpy()
     ref, ab = oracle_mod.rhs(medium_net, y[:40], T[:40], with_abs=True)
     _close(f, ref, ab)

