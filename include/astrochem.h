@@ -307,6 +307,14 @@ typedef struct {
                             workspace reserved for */
   double newton_tol;     /* corrector convergence tolerance in the weighted RMS
                             norm; <= 0 selects max(10 eps/rtol, min(0.03, sqrt(rtol))) */
+  const int32_t *cell_order; /* ac_integrate and ac_integrate_thermal: DEVICE
+                            [n_cells], the order in which the persistent
+                            workgroups take the cells (a permutation of
+                            0..n_cells-1; cells expected to take longest first
+                            shorten the run's tail), or NULL for index order.
+                            Each cell's results do not depend on it. Not
+                            checked: a repeated index integrates that cell
+                            twice, concurrently. */
 } ac_integ_opts;
 
 /* Per-cell counters written by the integrator ([n_cells][AC_NSTAT]). */

@@ -150,7 +150,8 @@ def _check_dev(t, shape, name: str):
 class IntegOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h0", C.c_double),
                 ("q_max", C.c_int32), ("max_steps", C.c_int32), ("adj_recompute", C.c_int32),
-                ("checkpoint_every", C.c_int32), ("newton_tol", C.c_double)]
+                ("checkpoint_every", C.c_int32), ("newton_tol", C.c_double),
+                ("cell_order", C.c_void_p)]
 
 
 EVENT_DTYPE = np.dtype([("type", np.int32), ("q", np.int32), ("val", np.float64)])
@@ -475,21 +476,29 @@ class Workspace:
             pass
 
     def integrate(self, y, T, t_end, rtol=1e-6, atol=1e-20, q_max=5, max_steps=100000, h0=0.0,
-                  log_alpha=None, tape_cap=0, plain=False, newton_tol=0.0, stream=None):
+                  log_alpha=None, tape_cap=0, plain=False, newton_tol=0.0, cell_order=None,
+                  stream=None):
         """Integrates y (device, in place) to t_end. Returns dict of device
         tensors: status [n], stats [n, NSTAT] and, with tape_cap > 0, the
-        recorded steps (tape [n, tape_cap] of EVENT_DTYPE bytes, tape_len)."""
+        recorded steps (tape [n, tape_cap] of EVENT_DTYPE bytes, tape_len).
+        cell_order: optional device int32 permutation of the cells, the
+        order in which the workgroups take them (e.g. longest expected
+        first); each cell's results do not depend on it."""
         import torch
         n = T.shape[0]
         _check_dev(T, self.net.cond_shape(n), "T")
         _check_dev(y, (n, self.net.n_species), "y")
         if log_alpha is not None:
             _check_dev(log_alpha, (self.net.n_reactions,), "log_alpha")
+        if cell_order is not None:
+            if (cell_order.dtype != torch.int32 or tuple(cell_order.shape) != (n,)
+                    or not cell_order.is_cuda or not cell_order.is_contiguous()):
+                raise ValueError("cell_order must be a contiguous device int32 tensor [n_cells]")
         dev = y.device
         status = torch.empty(n, dtype=torch.int32, device=dev)
         stats = torch.empty((n, NSTAT), dtype=torch.int32, device=dev)
         o = IntegOpts(float(rtol), float(atol), float(h0), int(q_max), int(max_steps), 0, 0,
-                      float(newton_tol))
+                      float(newton_tol), _ptr(cell_order))
         out = {"status": status, "stats": stats}
         if plain:
             check(lib.ac_integrate_plain(self.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T),

@@ -640,6 +640,7 @@ ac_status ac_integrate(ac_ws *ws, const double *log_alpha, int64_t n_cells, doub
   if (tape && (tape_cap <= 0 || !tape_len)) return fail(AC_EINVAL, "tape needs tape_cap > 0 and tape_len");
   ac::BdfParams P{opts->rtol, opts->atol, opts->h0, t_end, opts->q_max, opts->max_steps,
                    opts->newton_tol};
+  P.order = opts->cell_order;
   ac::CellOut out{cell_status, cell_stats};
   ac::TapeView tv{reinterpret_cast<ac::AcEvent *>(tape), tape ? tape_len : nullptr, tape ? tape_cap : 0};
   hipError_t e = ac::launch_bdf(ws->net->d, log_alpha, n_cells, y, T, nullptr, P, out, tv, ws->W,
@@ -656,6 +657,7 @@ ac_status ac_integrate_thermal(ac_ws *ws, const double *log_alpha, int64_t n_cel
   if (n_cells && !therm) return fail(AC_EINVAL, "null therm");
   ac::BdfParams P{opts->rtol, opts->atol, opts->h0, t_end, opts->q_max, opts->max_steps,
                    opts->newton_tol};
+  P.order = opts->cell_order;
   ac::CellOut out{cell_status, cell_stats};
   ac::TapeView tv{nullptr, nullptr, 0};
   hipError_t e = ac::launch_bdf(ws->net->d, log_alpha, n_cells, y, T, therm, P, out, tv, ws->W,

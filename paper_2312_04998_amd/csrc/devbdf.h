@@ -25,6 +25,7 @@ struct BdfParams {
   double rtol, atol, h0, t_end;
   int q_max, max_steps;
   double newton_tol;   // <= 0: max(10 eps/rtol, min(0.03, sqrt(rtol)))
+  const int32_t *order = nullptr;   // queue position -> cell, or null (index order)
 };
 
 struct CellOut {

@@ -89,11 +89,12 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
 
   for (int64_t iter = 0;; ++iter) {
     if (threadIdx.x == 0) {
-      s_cell = queue ? int64_t(atomicAdd(queue, 1u)) : int64_t(blockIdx.x) + iter * gridDim.x;
+      int64_t pos = queue ? int64_t(atomicAdd(queue, 1u)) : int64_t(blockIdx.x) + iter * gridDim.x;
       // progress for the host: a system-scope store to the pinned word
-      if (W.progress && s_cell < n_cells)
-        __hip_atomic_store(W.progress, unsigned(s_cell + 1), __ATOMIC_RELAXED,
+      if (W.progress && pos < n_cells)
+        __hip_atomic_store(W.progress, unsigned(pos + 1), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_SYSTEM);
+      s_cell = (P.order && pos < n_cells) ? int64_t(P.order[pos]) : pos;
     }
     __syncthreads();
     const int64_t cell = s_cell;

@@ -249,6 +249,31 @@ def test_queue_more_cells_than_slots(acm, torch_dev, oracle_mod, tiny):
     assert ok.all(), (bad[:5], o1["stats"][bad[:1, 0]].tolist(), steps[:, bad[:1, 0]].T.tolist())
 
 
+def test_cell_order_does_not_change_results(acm, torch_dev, tiny):
+    """The workgroups taking 29 cells in a shuffled order (3 slots) give the
+    same y, status and statistics bit for bit as index order; the progress
+    word ends at (about) the cell count; a malformed order is refused."""
+    torch = torch_dev
+    net, cells = tiny
+    rng = np.random.default_rng(11)
+    n = 29
+    y0 = np.repeat(cells.y0[:1], n, 0) * rng.uniform(0.5, 2.0, (n, 1))
+    T = np.exp(rng.uniform(np.log(10), np.log(300), n))
+    N = acm.Network.from_synth(net)
+    ws = acm.Workspace(N, n_slots=3)
+    t_end = 1e4 * YEAR_S
+    y1, y2 = _t(torch, y0), _t(torch, y0)
+    o1 = ws.integrate(y1, _t(torch, T), t_end)
+    perm = torch.from_numpy(rng.permutation(n).astype(np.int32)).cuda()
+    o2 = ws.integrate(y2, _t(torch, T), t_end, cell_order=perm)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2) and torch.equal(o1["status"], o2["status"])
+    assert torch.equal(o1["stats"], o2["stats"])
+    assert n - ws.n_slots < ws.progress() <= n    # workgroups report in taking order, roughly
+    with pytest.raises(ValueError):
+        ws.integrate(y2, _t(torch, T), t_end, cell_order=perm.to(torch.int64))
+
+
 def test_status_codes(acm, torch_dev, tiny):
     torch = torch_dev
     net, cells = tiny
