@@ -290,10 +290,11 @@ def scale_leg(torch, acm):
                     generator=torch.Generator("cuda").manual_seed(2))
     gy = torch.empty_like(y)
     gl = torch.empty(nr, dtype=torch.float64, device="cuda")
-    # the one-cell kernels take one workgroup per CU at this LDS size, so the
-    # workgroup size sets the waves per CU: both sizes timed, the faster kept
+    # the one-cell Jacobian takes one workgroup per CU at this LDS size, so the
+    # workgroup size sets its waves per CU: the library's own choice per
+    # kernel (0) and both fixed sizes timed, the fastest kept
     by_block = {}
-    for blk in (512, 1024):
+    for blk in (0, 512, 1024):
         N = acm.Network.from_synth(net, layout="sell", ordering="rcm", block=blk)
         tm = Timer(torch)
         for name, fn in (("rhs_jac", lambda: acm.ac_rhs_jac(N, None, y, T, dydt, jv)),

@@ -131,8 +131,10 @@ typedef struct {
   int32_t chunk;             /* max nonzeros per row chunk; 0 = default (32) */
   int32_t sell_c;            /* SELL slice width in chunks: 0 or 64 (one wavefront) */
   int32_t sell_sigma;        /* SELL sorting window in chunks; 0 = default (whole matrix) */
-  int32_t block;             /* threads per workgroup of the chemistry kernels: 256, 512
-                                or 1024; 0 = default (512) */
+  int32_t block;             /* threads per workgroup of the one-cell chemistry kernels:
+                                256, 512 or 1024; 0 = per kernel, 1024 when its LDS
+                                leaves room for one workgroup per CU, else 512 (the
+                                two-cells-per-pass kernels always run 1024) */
   const int8_t *rate_law;    /* host [n_reactions] ac_rate_law codes, or NULL (every reaction
                                 AC_LAW_KOOIJ, per-cell conditions = T only) */
   const double *heat;        /* host [n_reactions] energy released per reaction event [erg]

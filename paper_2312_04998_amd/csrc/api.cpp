@@ -218,7 +218,7 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
   d.nr = H.nr;
   d.nnz_j = int(H.j_col.size());
   d.layout = H.layout;
-  d.block = desc->block ? desc->block : 512;
+  d.block = desc->block;   // 0: chosen per kernel from its LDS size
   d.n_cond = H.law.empty() ? 1 : AC_NCOND;
   d.log_alpha = at<double>(b, o_la);
   d.beta = at<double>(b, o_be);

@@ -552,6 +552,14 @@ size_t rhs_lds_bytes(const DNet &n) {
 #define AC_DISPATCH_NT(nt, CALL) \
   ((nt) == 256 ? CALL(256) : (nt) == 1024 ? CALL(1024) : CALL(512))
 
+// The workgroup size of a one-cell kernel using `lds` bytes: the network's,
+// or when it asks for none, 1024 threads if the LDS leaves room for only
+// one workgroup per CU (so that the CU still runs 16 waves), else 512.
+static int block_for(const DNet &n, size_t lds) {
+  if (n.block) return n.block;
+  return lds > 80 * 1024 ? 1024 : 512;
+}
+
 template <int NT>
 static hipError_t rates_nt(const DNet &n, const double *la, int64_t n_cells, const double *T,
                            double *k, hipStream_t st) {
@@ -564,7 +572,7 @@ hipError_t launch_rates(const DNet &n, const double *la, int64_t n_cells, const 
                         double *k, hipStream_t st) {
   if (n_cells == 0) return hipSuccess;
 #define CALL(NT) rates_nt<NT>(n, la, n_cells, T, k, st)
-  return AC_DISPATCH_NT(n.block, CALL);
+  return AC_DISPATCH_NT(block_for(n, 0), CALL);
 #undef CALL
 }
 
@@ -606,7 +614,7 @@ hipError_t launch_rhs(const DNet &n, const double *la, int64_t n_cells, const do
     return hipGetLastError();
   }
 #define CALL(NT) rhs_nt<NT>(n, la, n_cells, y, T, k, dydt, st)
-  return AC_DISPATCH_NT(n.block, CALL);
+  return AC_DISPATCH_NT(block_for(n, rhs_lds_bytes(n)), CALL);
 #undef CALL
 }
 
@@ -650,7 +658,9 @@ hipError_t launch_jac(const DNet &n, const double *la, int64_t n_cells, const do
     return hipGetLastError();
   }
 #define CALL(NT) jac_nt<NT>(n, la, n_cells, y, T, jvals, st)
-  return AC_DISPATCH_NT(n.block, CALL);
+  return AC_DISPATCH_NT(
+      block_for(n, sizeof(double) * size_t(n.ns + n.nr + (n.jtail.n_slot > 0 ? n.jtail.n_slot : 1))),
+      CALL);
 #undef CALL
 }
 
@@ -716,7 +726,10 @@ hipError_t launch_vjp(const DNet &n, const double *la, int64_t n_cells, const do
     return hipGetLastError();
   }
 #define CALL(NT) vjp_nt<NT>(n, la, n_cells, y, T, v, gy, g_logalpha, part, part_rows, st)
-  return AC_DISPATCH_NT(n.block, CALL);
+  return AC_DISPATCH_NT(
+      block_for(n, sizeof(double) *
+                       size_t(2 * n.ns + n.nr + (n.gy.n_slot > 0 ? n.gy.n_slot : 1))),
+      CALL);
 #undef CALL
 }
 

@@ -189,6 +189,33 @@ def test_large_network(acm, torch_dev, oracle_mod):
     _close(gy.cpu().numpy(), ref_gy, np.einsum("ci,cia->ca", np.abs(v[:9]), abJ))
 
 
+def test_one_cell_kernels_agree_across_workgroup_sizes(acm, torch_dev, oracle_mod):
+    """700 / 8000 network (too large for two cells per pass): the one-cell
+    RHS, Jacobian and VJP kernels give the same bits at 256, 512 and 1024
+    threads and at the library's own choice (0): the workgroup size only
+    changes which thread sums a chunk, not the order of any sum."""
+    torch = torch_dev
+    net, _ = synthnet.workload("large", n_cells=1)
+    cells = synthnet.make_cells(net, 21, synthnet.SEED_BASE + 6)
+    y, T = _t(torch, cells.y0), _t(torch, cells.T)
+    v = _t(torch, np.random.default_rng(6).standard_normal(cells.y0.shape))
+    outs = {}
+    for layout in ("csr", "runs"):
+        for blk in (256, 512, 1024, 0):
+            N = acm.Network.from_synth(net, layout=layout, ordering="rcm", block=blk)
+            gy, gl = N.vjp(y, T, v)
+            outs[(layout, blk)] = (N.rhs(y, T), N.jac(y[:1], T[:1]), N.jac(y, T), gy, gl)
+            N.close()
+        ref = outs[(layout, 512)]
+        for blk in (256, 1024, 0):
+            for a, b in zip(outs[(layout, blk)], ref):
+                assert torch.equal(a, b), (layout, blk)
+    # and the shared result is the oracle's
+    f = outs[("csr", 0)][0].cpu().numpy()
+    ref, ab = oracle_mod.rhs(net, cells.y0, cells.T, with_abs=True)
+    _close(f, ref, ab)
+
+
 def test_edge_cases(acm, torch_dev, oracle_mod):
     torch = torch_dev
     # paper example plus a species that takes part in nothing (empty row)
