@@ -168,6 +168,18 @@ ac_status ac_net_jac_pattern(const ac_net *net, int32_t *row_ptr /*n_species+1*/
                              int32_t *col /*nnz_j*/);
 /* Traversal order of species rows (perm[k] = species visited k-th). */
 ac_status ac_net_row_order(const ac_net *net, int32_t *perm /*n_species*/);
+/* Plan of the integrator's Newton solve (AC_LINSOLVE_AUTO, built with the
+ * network from the Jacobian pattern): the number of front species swept
+ * sparsely, the sweep levels, the stored sparse values and sweep updates per
+ * factorisation, the order of the species (order[p] = species at position
+ * p, the front first, then the densely factored tail), and the modelled
+ * cost of a factorisation and its solves relative to one dense LU of the
+ * whole matrix (< 1 means the plan is expected to be faster). The front is
+ * chosen by the minimum-degree order of the pattern, as in the sparse solve
+ * of DLSODES (Sec. 3). Any output may be NULL. */
+ac_status ac_net_front_info(const ac_net *net, int32_t *n_front, int32_t *n_levels,
+                            int64_t *n_values, int64_t *n_updates, double *cost_ratio,
+                            int32_t *order /*n_species*/);
 
 /* Host-side storage builder for any small integer matrix given densely
  * (row-major n_rows x n_cols), exposing the formats of Sec. 2.2 with
@@ -317,7 +329,19 @@ typedef struct {
                             Each cell's results do not depend on it. Not
                             checked: a repeated index integrates that cell
                             twice, concurrently. */
+  int32_t linear_solver; /* ac_linear_solver: how the Newton matrix is factored */
 } ac_integ_opts;
+
+/* Newton solves of the integrator and the adjoint. DLSODES, the integrator
+ * of the paper (Sec. 3), factors the sparse Newton matrix under a
+ * minimum-degree order without pivoting. AUTO does that for the species the
+ * order eliminates first (a Gauss-Jordan sweep of that sparse front, in
+ * levels of independent pivots, chosen by structure at network build) and
+ * factors the Schur complement left over by the remaining, densely coupled
+ * species with partial pivoting on the matrix cores. DENSE factors the whole
+ * matrix with partial pivoting. The temperature-coupled mode is always
+ * DENSE (its temperature row and column are full). */
+typedef enum { AC_LINSOLVE_AUTO = 0, AC_LINSOLVE_DENSE = 1 } ac_linear_solver;
 
 /* Per-cell counters written by the integrator ([n_cells][AC_NSTAT]). */
 enum { AC_STAT_STEPS = 0, AC_STAT_REJECT_ERR, AC_STAT_REJECT_NEWTON, AC_STAT_NEWTON_ITERS,

@@ -62,6 +62,7 @@ def _load() -> C.CDLL:
         "ac_net_stoich": [vp, vp, vp, vp],
         "ac_net_jac_pattern": [vp, vp, vp],
         "ac_net_row_order": [vp, vp],
+        "ac_net_front_info": [vp, vp, vp, vp, vp, vp, vp],
         "ac_sparse_format": [i32, i32, vp, i32, i32, vp, vp, vp, vp, vp],
         "ac_rates": [vp, vp, i64, vp, vp, vp],
         "ac_rhs": [vp, vp, i64, vp, vp, vp, vp],
@@ -151,7 +152,16 @@ class IntegOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h0", C.c_double),
                 ("q_max", C.c_int32), ("max_steps", C.c_int32), ("adj_recompute", C.c_int32),
                 ("checkpoint_every", C.c_int32), ("newton_tol", C.c_double),
-                ("cell_order", C.c_void_p)]
+                ("cell_order", C.c_void_p), ("linear_solver", C.c_int32)]
+
+
+LINEAR_SOLVERS = {"auto": 0, "dense": 1}   # ac_linear_solver
+
+
+def _solver(name):
+    if name not in LINEAR_SOLVERS:
+        raise ValueError(f"linear_solver must be one of {sorted(LINEAR_SOLVERS)}")
+    return LINEAR_SOLVERS[name]
 
 
 EVENT_DTYPE = np.dtype([("type", np.int32), ("q", np.int32), ("val", np.float64)])
@@ -230,6 +240,20 @@ class Network:
         col = np.zeros(max(self.nnz_j, 1), np.int32)
         check(lib.ac_net_jac_pattern(self.handle, _ptr(rp), _ptr(col)), "ac_net_jac_pattern")
         return rp, col[:self.nnz_j]
+
+    def front_info(self):
+        """The integrator's Newton-solve plan: dict with n_front, n_levels,
+        n_values, n_updates, cost_ratio (modelled, vs one dense LU) and order
+        (positions -> species, front first)."""
+        n1, nl = C.c_int32(), C.c_int32()
+        nv, nu = C.c_int64(), C.c_int64()
+        cr = C.c_double()
+        order = np.empty(self.n_species, np.int32)
+        check(lib.ac_net_front_info(self.handle, C.byref(n1), C.byref(nl), C.byref(nv), C.byref(nu),
+                                    C.byref(cr), order.ctypes.data_as(C.c_void_p)),
+              "ac_net_front_info")
+        return {"n_front": n1.value, "n_levels": nl.value, "n_values": nv.value,
+                "n_updates": nu.value, "cost_ratio": cr.value, "order": order}
 
     def row_order(self):
         p = np.zeros(self.n_species, np.int32)
@@ -477,13 +501,15 @@ class Workspace:
 
     def integrate(self, y, T, t_end, rtol=1e-6, atol=1e-20, q_max=5, max_steps=100000, h0=0.0,
                   log_alpha=None, tape_cap=0, plain=False, newton_tol=0.0, cell_order=None,
-                  stream=None):
+                  linear_solver="auto", stream=None):
         """Integrates y (device, in place) to t_end. Returns dict of device
         tensors: status [n], stats [n, NSTAT] and, with tape_cap > 0, the
         recorded steps (tape [n, tape_cap] of EVENT_DTYPE bytes, tape_len).
         cell_order: optional device int32 permutation of the cells, the
         order in which the workgroups take them (e.g. longest expected
-        first); each cell's results do not depend on it."""
+        first); each cell's results do not depend on it. linear_solver:
+        "auto" (sparse front swept, dense Schur tail) or "dense" (one
+        pivoted LU of the whole Newton matrix)."""
         import torch
         n = T.shape[0]
         _check_dev(T, self.net.cond_shape(n), "T")
@@ -498,7 +524,7 @@ class Workspace:
         status = torch.empty(n, dtype=torch.int32, device=dev)
         stats = torch.empty((n, NSTAT), dtype=torch.int32, device=dev)
         o = IntegOpts(float(rtol), float(atol), float(h0), int(q_max), int(max_steps), 0, 0,
-                      float(newton_tol), _ptr(cell_order))
+                      float(newton_tol), _ptr(cell_order), _solver(linear_solver))
         out = {"status": status, "stats": stats}
         if plain:
             check(lib.ac_integrate_plain(self.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T),
@@ -518,7 +544,7 @@ class Workspace:
 
     def adjoint(self, y0, T, tape, tape_len, lam, rtol=1e-6, atol=1e-20, log_alpha=None,
                 want_glog=True, want_cells=False, want_y=False, recompute=False,
-                checkpoint_every=0, stream=None):
+                checkpoint_every=0, linear_solver="auto", stream=None):
         """Discrete adjoint (ac_integrate_adjoint) of L = sum <lam, y(t_end)>
         over the recorded tape of an earlier integrate(..., tape_cap=...).
         Returns dict of device tensors: dL_dy0 [n, ns], status [n], stats
@@ -558,7 +584,7 @@ class Workspace:
             yf = torch.empty_like(y0)
             out["y_final"] = yf
         o = IntegOpts(float(rtol), float(atol), 0.0, 5, 1, 1 if recompute else 0,
-                      int(checkpoint_every))
+                      int(checkpoint_every), 0.0, None, _solver(linear_solver))
         check(lib.ac_integrate_adjoint(self.handle, _ptr(log_alpha), n, _ptr(y0), _ptr(T),
                                        C.byref(o), _ptr(tape), int(tape.shape[1]),
                                        _ptr(tape_len), _ptr(lam), _ptr(yf), _ptr(gy0),
@@ -567,7 +593,8 @@ class Workspace:
         return out
 
 
-def _replay(ws, y0, T, tape, tape_len, rtol=1e-6, atol=1e-20, log_alpha=None, stream=None):
+def _replay(ws, y0, T, tape, tape_len, rtol=1e-6, atol=1e-20, log_alpha=None,
+            linear_solver="auto", stream=None):
     import torch
     n, ns = T.shape[0], ws.net.n_species
     _check_dev(T, ws.net.cond_shape(n), "T")
@@ -579,7 +606,8 @@ def _replay(ws, y0, T, tape, tape_len, rtol=1e-6, atol=1e-20, log_alpha=None, st
     yf = torch.empty_like(y0)
     status = torch.empty(n, dtype=torch.int32, device=y0.device)
     ws._ensure_adjoint(int(tape.shape[1]), ws.checkpoint_every)
-    o = IntegOpts(float(rtol), float(atol), 0.0, 5, 1, 1, int(ws.checkpoint_every))
+    o = IntegOpts(float(rtol), float(atol), 0.0, 5, 1, 1, int(ws.checkpoint_every), 0.0, None,
+                  _solver(linear_solver))
     check(lib.ac_replay(ws.handle, _ptr(log_alpha), n, _ptr(y0), _ptr(T), C.byref(o), _ptr(tape),
                         int(tape.shape[1]), _ptr(tape_len), _ptr(yf), _ptr(status), None,
                         _stream(stream)), "ac_replay")

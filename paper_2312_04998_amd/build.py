@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libastrochem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "netbuild.cpp", "kernels_chem.hip", "kernels_bdf.hip", "kernels_adj.hip",
+SOURCES = ["api.cpp", "netbuild.cpp", "frontlu.cpp", "kernels_chem.hip", "kernels_bdf.hip", "kernels_adj.hip",
            "static_scratch.hip", "kernels_thermal.hip"]
 
 COMMON = [

@@ -187,6 +187,12 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
   const size_t o_h0 = p.add(H.jhead0), o_h1 = p.add(H.jhead1), o_td = p.add(H.jtaildesc);
   const size_t o_er = p.add(H.jent_row), o_ec = p.add(H.j_col);
   const size_t o_ht = p.add(H.heat);
+  const ac::FrontPlan &FP = H.front;
+  const size_t o_fperm = p.add(FP.perm), o_flev = p.add(FP.lev_ptr), o_frp = p.add(FP.row_ptr),
+               o_fcol = p.add(FP.col), o_frs = p.add(FP.rsplit), o_fdg = p.add(FP.vdiag),
+               o_fcp = p.add(FP.cptr), o_fcr = p.add(FP.crow), o_fci = p.add(FP.cidx),
+               o_fcs = p.add(FP.csplit), o_fasm = p.add(FP.asm_dst), o_ftp = p.add(FP.tg_ptr),
+               o_ftg = p.add(FP.tgt), o_fop = p.add(FP.op_ptr), o_fops = p.add(FP.ops);
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();
@@ -238,6 +244,29 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
   d.jent_row = at<int32_t>(b, o_er);
   d.jent_col = at<int32_t>(b, o_ec);
   d.heat = H.heat.empty() ? nullptr : at<double>(b, o_ht);
+  ac::DFront &f = d.fr;
+  f.n = FP.n;
+  f.n1 = FP.n1;
+  f.n2 = FP.n2;
+  f.lda2 = FP.lda2;
+  f.vofs = FP.vofs;
+  f.nv = FP.nv;
+  f.n_lev = FP.n_lev;
+  f.perm = at<int32_t>(b, o_fperm);
+  f.lev_ptr = at<int32_t>(b, o_flev);
+  f.row_ptr = at<int32_t>(b, o_frp);
+  f.col = at<int32_t>(b, o_fcol);
+  f.rsplit = at<int32_t>(b, o_frs);
+  f.vdiag = at<int32_t>(b, o_fdg);
+  f.cptr = at<int32_t>(b, o_fcp);
+  f.crow = at<int32_t>(b, o_fcr);
+  f.cidx = at<int32_t>(b, o_fci);
+  f.csplit = at<int32_t>(b, o_fcs);
+  f.asm_dst = at<int32_t>(b, o_fasm);
+  f.tg_ptr = at<int32_t>(b, o_ftp);
+  f.tgt = at<int32_t>(b, o_ftg);
+  f.op_ptr = at<int32_t>(b, o_fop);
+  f.ops = at<int2>(b, o_fops);
   *out = net;
   return AC_OK;
 }
@@ -279,6 +308,20 @@ ac_status ac_net_jac_pattern(const ac_net *net, int32_t *row_ptr, int32_t *col) 
 ac_status ac_net_row_order(const ac_net *net, int32_t *perm) {
   if (!net || !perm) return fail(AC_EINVAL, "null argument");
   std::copy(net->host.perm.begin(), net->host.perm.end(), perm);
+  return AC_OK;
+}
+
+ac_status ac_net_front_info(const ac_net *net, int32_t *n_front, int32_t *n_levels,
+                            int64_t *n_values, int64_t *n_updates, double *cost_ratio,
+                            int32_t *order) {
+  if (!net) return fail(AC_EINVAL, "null network");
+  const ac::FrontPlan &F = net->host.front;
+  if (n_front) *n_front = F.n1;
+  if (n_levels) *n_levels = F.n_lev;
+  if (n_values) *n_values = F.nv;
+  if (n_updates) *n_updates = int64_t(F.ops.size() / 2);
+  if (cost_ratio) *cost_ratio = F.cost_dense > 0.0 ? F.cost_front / F.cost_dense : 1.0;
+  if (order) std::copy(F.perm.begin(), F.perm.end(), order);
   return AC_OK;
 }
 
@@ -526,9 +569,11 @@ ac_status ac_ws_create(const ac_net *net, int32_t n_slots, ac_ws **out) {
   // Newton matrix, Jacobian pattern values plus its T column, T row and
   // corner, difference array, pivots and permutation
   const int ns = net->d.ns, nv = ns + 1, nr = net->d.nr, nnz = net->d.nnz_j;
-  const int lda = (nv + 15) / 16 * 16;
+  const int lda = ac::newton_lda(ns);
   auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t m_b = r256(sizeof(double) * size_t(nv) * lda);
+  // also holds the Schur tail and the swept front values (the plan is
+  // sized to this region)
+  const size_t m_b = r256(sizeof(double) * ac::newton_region_doubles(ns));
   const size_t j_b = r256(sizeof(double) * (size_t(nnz) + 2 * size_t(ns) + 1));
   const size_t t_b = r256(sizeof(double) * size_t(std::max(1, net->host.jtail.n_slot)));
   const size_t d_b = r256(sizeof(double) * size_t(8) * nv);
@@ -629,7 +674,15 @@ static ac_status integ_args(ac_ws *ws, int64_t n_cells, const double *y, const d
   if (o->q_max < 1 || o->q_max > 5) return fail(AC_EINVAL, "q_max must be 1..5");
   if (o->max_steps < 1) return fail(AC_EINVAL, "max_steps must be >= 1");
   if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(AC_EINVAL, "t_end must be finite and >= 0");
+  if (o->linear_solver != AC_LINSOLVE_AUTO && o->linear_solver != AC_LINSOLVE_DENSE)
+    return fail(AC_EINVAL, "linear_solver must be AC_LINSOLVE_AUTO or AC_LINSOLVE_DENSE");
   return AC_OK;
+}
+
+static ac::BdfParams bdf_params(const ac_integ_opts *o, double t_end) {
+  ac::BdfParams P{o->rtol, o->atol, o->h0, t_end, o->q_max, o->max_steps, o->newton_tol};
+  P.linear_solver = o->linear_solver;
+  return P;
 }
 
 ac_status ac_integrate(ac_ws *ws, const double *log_alpha, int64_t n_cells, double *y,
@@ -638,8 +691,7 @@ ac_status ac_integrate(ac_ws *ws, const double *log_alpha, int64_t n_cells, doub
                        int32_t tape_cap, int32_t *tape_len, ac_stream stream) {
   if (ac_status s = integ_args(ws, n_cells, y, T, t_end, opts)) return s;
   if (tape && (tape_cap <= 0 || !tape_len)) return fail(AC_EINVAL, "tape needs tape_cap > 0 and tape_len");
-  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, t_end, opts->q_max, opts->max_steps,
-                   opts->newton_tol};
+  ac::BdfParams P = bdf_params(opts, t_end);
   P.order = opts->cell_order;
   ac::CellOut out{cell_status, cell_stats};
   ac::TapeView tv{reinterpret_cast<ac::AcEvent *>(tape), tape ? tape_len : nullptr, tape ? tape_cap : 0};
@@ -655,8 +707,7 @@ ac_status ac_integrate_thermal(ac_ws *ws, const double *log_alpha, int64_t n_cel
                                int32_t *cell_stats, ac_stream stream) {
   if (ac_status s = integ_args(ws, n_cells, y, T, t_end, opts)) return s;
   if (n_cells && !therm) return fail(AC_EINVAL, "null therm");
-  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, t_end, opts->q_max, opts->max_steps,
-                   opts->newton_tol};
+  ac::BdfParams P = bdf_params(opts, t_end);
   P.order = opts->cell_order;
   ac::CellOut out{cell_status, cell_stats};
   ac::TapeView tv{nullptr, nullptr, 0};
@@ -669,8 +720,7 @@ ac_status ac_integrate_plain(ac_ws *ws, const double *log_alpha, int64_t n_cells
                              const double *T, double t_end, const ac_integ_opts *opts,
                              int32_t *cell_status, int32_t *cell_stats, ac_stream stream) {
   if (ac_status s = integ_args(ws, n_cells, y, T, t_end, opts)) return s;
-  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, t_end, opts->q_max, opts->max_steps,
-                   opts->newton_tol};
+  ac::BdfParams P = bdf_params(opts, t_end);
   const int ns = ws->net->d.ns;
   for (int64_t c = 0; c < n_cells; ++c) {
     ac::CellOut out{cell_status ? cell_status + c : nullptr,
@@ -792,8 +842,7 @@ ac_status ac_replay(ac_ws *ws, const double *log_alpha, int64_t n_cells, const d
     return fail(AC_EINVAL, "null tape, tape_len or y_final");
   if (!n_cells) return AC_OK;
   if (ac_status s = adj_capacity(ws, tape_cap, opts)) return s;
-  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, 0.0, opts->q_max, opts->max_steps,
-                   opts->newton_tol};
+  ac::BdfParams P = bdf_params(opts, 0.0);
   ac::AdjIO io{reinterpret_cast<const ac::AcEvent *>(tape), tape_len, tape_cap, y0, T, nullptr,
                y_final, nullptr, nullptr, cell_status, cell_stats};
   hipError_t e = ac::launch_adjoint(ws->net->d, log_alpha, n_cells, io, P, ws->W, ws->A,
@@ -826,8 +875,7 @@ ac_status ac_integrate_adjoint(ac_ws *ws, const double *log_alpha, int64_t n_cel
                               "(ac_adj_reserve.max_cells > 0)");
   ac::AdjView A = ws->A;
   if (opts->adj_recompute) A.all_states = 0;   // segments recomputed from checkpoints
-  ac::BdfParams P{opts->rtol, opts->atol, opts->h0, 0.0, opts->q_max, opts->max_steps,
-                   opts->newton_tol};
+  ac::BdfParams P = bdf_params(opts, 0.0);
   // cells in chunks: all at once into the caller's rows, or max_cells at a
   // time into the workspace's rows, each chunk's rows added to the sum in
   // cell order (the same order as one pass over every row)

@@ -26,6 +26,7 @@ struct BdfParams {
   int q_max, max_steps;
   double newton_tol;   // <= 0: max(10 eps/rtol, min(0.03, sqrt(rtol)))
   const int32_t *order = nullptr;   // queue position -> cell, or null (index order)
+  int linear_solver = 0;   // AC_LINSOLVE_*
 };
 
 struct CellOut {

@@ -26,6 +26,15 @@ struct DSched {
   const int32_t *run_slot, *seg_run;
 };
 
+// Plan of the integrator's Newton solve: sparse front swept in levels, dense
+// Schur tail (frontlu.h). n = 0: no plan.
+struct DFront {
+  int n, n1, n2, lda2, vofs, nv, n_lev;
+  const int32_t *perm, *lev_ptr, *row_ptr, *col, *rsplit, *vdiag, *cptr, *crow, *cidx, *csplit;
+  const int32_t *asm_dst, *tg_ptr, *tgt, *op_ptr;
+  const int2 *ops;
+};
+
 struct DNet {
   int ns, nr, nnz_j, layout, block;
   int n_cond;                  // doubles of per-cell conditions: 1 (T) or AC_NCOND
@@ -37,6 +46,7 @@ struct DNet {
   const uint32_t *jhead0, *jhead1, *jtaildesc;
   const int32_t *jent_row, *jent_col;   // row and column of every pattern entry
   const double *heat;          // [nr] energy per reaction event (temperature-coupled mode) or null
+  DFront fr;
 };
 
 // Launchers (kernels_chem.hip). All enqueue on `stream`; return hipError_t.

@@ -7,6 +7,7 @@
 #include "devchem.h"
 #include "devla.h"
 #include "devbdf.h"
+#include "devfront.h"
 
 namespace ac {
 
@@ -60,6 +61,9 @@ struct CellCtx {
   double cv = 1.0, Tb = 0.0, lam = 0.0;
   const double *la_over = nullptr;
   double *Jaux = nullptr;
+  // Newton matrix held as a swept sparse front and a dense Schur tail
+  // (front_factor / front_solve) instead of one dense LU
+  bool front = false;
 };
 
 template <int NT>
@@ -139,10 +143,17 @@ __device__ __forceinline__ void cell_jac(CellCtx &cx, const double *y) {
   cx.cnt[ST_JAC]++;
 }
 
-// M = I - c J (dense, row-major, lda) from the pattern values, then LU.
+// M = I - c J from the pattern values, then its factors: the sparse front
+// and Schur tail when cx.front, else the dense row-major LU (lda).
 template <int NT>
 __device__ __forceinline__ void cell_factor(CellCtx &cx, double c) {
   const DNet &n = *cx.n;
+  if (cx.front) {
+    cx.lu_info = front_factor<NT>(n, cx.Jg, c, cx.M, cx.piv, cx.perm, cx.scr, cx.red, cx.redi,
+                                  cx.ipiv);
+    cx.cnt[ST_LU]++;
+    return;
+  }
   const int ns = n.ns, lda = cx.lda;
   for (int e = threadIdx.x; e < ns * lda; e += NT) {
     const int i = e / lda, a = e - i * lda;
@@ -275,6 +286,16 @@ template <int NT, bool TH>
 __device__ __forceinline__ void cell_factor_any(CellCtx &cx, double c) {
   if (TH) cell_factor_th<NT>(cx, c);
   else cell_factor<NT>(cx, c);
+}
+
+// x = M^-1 x (or M^-T x) with the factors of cell_factor_any; x in LDS,
+// cx.tmp and cx.scr as scratch.
+template <int NT, bool TH>
+__device__ __forceinline__ void cell_solve(CellCtx &cx, double *x, bool trans) {
+  if (!TH && cx.front)
+    front_solve<NT>(cx.n->fr, cx.M, cx.perm, x, cx.tmp, trans, cx.scr);
+  else
+    wg_solve<NT>(cx.M, cx.lda, cx.n->ns + (TH ? 1 : 0), cx.perm, x, cx.tmp, trans, cx.scr);
 }
 
 // Resampling matrix for a step change by `factor` (Shampine & Reichelt

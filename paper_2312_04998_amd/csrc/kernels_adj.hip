@@ -74,7 +74,7 @@ __device__ __forceinline__ void replay_step(CellCtx &cx, const AdjVecs &v, int q
     cx.cnt[ST_NEWTON]++;
     for (int x = threadIdx.x; x < ns; x += NT) v.dy[x] = -(v.dd[x] - c * v.f[x] + v.psi[x]);
     __syncthreads();
-    wg_solve<NT>(cx.M, cx.lda, ns, cx.perm, v.dy, cx.tmp, false, cx.scr);
+    cell_solve<NT, false>(cx, v.dy, false);
     if (c != cM) {
       const double corr = 2.0 / (1.0 + c / cM);
       for (int x = threadIdx.x; x < ns; x += NT) v.dy[x] *= corr;
@@ -163,7 +163,7 @@ __device__ __forceinline__ void reverse_step(CellCtx &cx, const AdjVecs &v, doub
   // w = M(y)^{-T} dbar with M refactored at the converged y
   cell_jac<NT>(cx, v.yn);
   cell_factor<NT>(cx, c);
-  wg_solve<NT>(cx.M, cx.lda, ns, cx.perm, v.dy, cx.tmp, true, cx.scr);
+  cell_solve<NT, false>(cx, v.dy, true);
   cell_vjp<NT>(cx, v.yn, v.dy, v.f, grow, c);
   double gam_m[QMAX + 1];
 #pragma unroll
@@ -206,6 +206,7 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
   cx.red = red;
   cx.redi = redi;
   cx.ipiv = ipiv;
+  cx.front = P.linear_solver == AC_LINSOLVE_AUTO && n.fr.n == n.ns;
   double *Db = A.Db + slot * A.db_stride;
   double *ck = A.ck + slot * A.ck_stride;
   int *ckev = A.ckev + slot * A.ckev_stride;

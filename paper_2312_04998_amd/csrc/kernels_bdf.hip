@@ -82,6 +82,7 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
   cx.nc = n.n_cond;
   cx.la_over = la_over;
   cx.Jaux = cx.Jg + n.nnz_j;
+  cx.front = !TH && P.linear_solver == AC_LINSOLVE_AUTO && n.fr.n == n.ns;
   const double rtol = P.rtol, atol = P.atol, t_end = P.t_end;
   const double tol = P.newton_tol > 0.0
                          ? P.newton_tol
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
               if (nonfin) break;
               for (int x = threadIdx.x; x < ns; x += NT) dy[x] = c * f[x] - psi[x] - dd[x];
               __syncthreads();
-              wg_solve<NT>(cx.M, cx.lda, ns, cx.perm, dy, cx.tmp, false, cx.scr);
+              cell_solve<NT, TH>(cx, dy, false);
               if (corr != 1.0) {
                 for (int x = threadIdx.x; x < ns; x += NT) dy[x] *= corr;
                 __syncthreads();

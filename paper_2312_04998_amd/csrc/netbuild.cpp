@@ -426,6 +426,7 @@ std::string build_network(int ns, int nr, const int32_t *reactants, const int32_
       half[q++] = uint16_t(H.s_row[p] | ((H.s_cval[p] & 31) << 11));
     std::memcpy(p2, half, sizeof(half));
   }
+  H.front = build_front_plan(ns, H.j_row_ptr, H.j_col, newton_region_doubles(ns));
   *code = AC_OK;
   return "";
 }

@@ -6,6 +6,8 @@
 #include <string>
 #include <vector>
 
+#include "frontlu.h"
+
 namespace ac {
 
 // A packed term of a segmented sum: value = coef * A[j] * (b == NONE ? 1 : y[b]).
@@ -92,8 +94,14 @@ struct HostNet {
   std::vector<int32_t> jent_row;      // row of every pattern entry (columns: j_col)
   Schedule jtail;
   Schedule gy;                        // species a: items (j, other reactant, mult) over slots of a
+  FrontPlan front;                    // the integrator's Newton solve (sparse front, dense tail)
   int layout = 0, ordering = 0;
 };
+
+// Doubles of an integrator slot's Newton-matrix region: (ns + 1) rows
+// (room for the temperature-coupled state) of lda = ns + 1 rounded up to 16.
+inline int newton_lda(int ns) { return (ns + 1 + 15) / 16 * 16; }
+inline size_t newton_region_doubles(int ns) { return size_t(ns + 1) * size_t(newton_lda(ns)); }
 
 // Returns an empty string on success, else the reason (code in *code).
 std::string build_network(int ns, int nr, const int32_t *reactants, const int32_t *products,

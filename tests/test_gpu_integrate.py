@@ -183,16 +183,29 @@ def test_tiny_network_parity(acm, torch_dev, oracle_mod, tiny, q_max, years):
 STRICT_FLOOR_MEDIUM = 0.95
 
 
-def test_medium_network_parity(acm, torch_dev, oracle_mod, medium):
+MEDIUM_IDX = [0, 5, 9]
+
+
+@pytest.fixture(scope="module")
+def medium_ref(oracle_mod, medium):
+    net, cells = medium
+    return oracle_with_envelope(oracle_mod, net, cells.y0[MEDIUM_IDX], cells.T[MEDIUM_IDX],
+                                1e6 * YEAR_S, k=8)
+
+
+@pytest.mark.parametrize("solver", ["auto", "dense"])
+def test_medium_network_parity(acm, torch_dev, medium, medium_ref, solver):
     """Paper-sized network (470 species / 4600 reactions), BDF 1-5 to 1e6 yr,
-    free running on both sides; 8 perturbed oracle reruns set the envelope."""
+    free running on both sides; 8 perturbed oracle reruns set the envelope.
+    Both Newton solves: the sparse front with a dense Schur tail (auto) and
+    one pivoted LU of the whole matrix (dense)."""
     torch = torch_dev
     net, cells = medium
-    idx = [0, 5, 9]
+    idx = MEDIUM_IDX
     y0, T = cells.y0[idx], cells.T[idx]
     t_end = 1e6 * YEAR_S
-    y, out, _ = _run(acm, torch, net, y0, T, t_end)
-    ref, env, steps = oracle_with_envelope(oracle_mod, net, y0, T, t_end, k=8)
+    y, out, _ = _run(acm, torch, net, y0, T, t_end, linear_solver=solver)
+    ref, env, steps = medium_ref
     assert out["status"].tolist() == ref["status"].tolist() == [0] * len(idx)
     bad = ~_agree(y, ref["y"], envelope=env)
     assert not bad.any(), (np.argwhere(bad)[:5], out["stats"], ref["stats"])

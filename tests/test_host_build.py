@@ -244,3 +244,35 @@ def test_lu_size_limit(acm):
     with pytest.raises(acm.AstrochemError) as e:
         acm.ac_lu_factor(A, piv, stream=0)   # rejected on the host, nothing launched
     assert e.value.status == acm.AC_ELIMIT
+
+
+def test_front_plan(acm, medium_net, tiny):
+    """The integrator's Newton-solve plan: a permutation of the species with
+    the front first, starting at a species of least degree in the symmetric
+    pattern of I - c J (minimum degree, ties to the smaller index), a front
+    strictly between empty and everything on the paper-sized network, every
+    pattern entry of a front row or column among the stored sparse values,
+    and a modelled cost below one dense LU."""
+    for net in (medium_net, tiny[0]):
+        N = acm.Network.from_synth(net)
+        fi = N.front_info()
+        ns = N.n_species
+        order = fi["order"]
+        assert sorted(order.tolist()) == list(range(ns))
+        assert 0 < fi["n_front"] < ns and fi["n_levels"] >= 1
+        assert fi["cost_ratio"] < 1.0
+        rp, col = N.jac_pattern()
+        rows = np.repeat(np.arange(ns), np.diff(rp))
+        P = sp.coo_matrix((np.ones(len(col)), (rows, col)), shape=(ns, ns)).tocsr()
+        G = ((P + P.T + sp.eye(ns)) != 0).astype(int)
+        deg = np.asarray(G.sum(1)).ravel()
+        assert order[0] == int(np.flatnonzero(deg == deg.min())[0])
+        pos = np.empty(ns, int)
+        pos[order] = np.arange(ns)
+        in_front = (pos[rows] < fi["n_front"]) | (pos[col] < fi["n_front"])
+        diag_front = fi["n_front"] - np.count_nonzero(in_front & (rows == col))
+        assert fi["n_values"] >= np.count_nonzero(in_front) + diag_front
+        N.close()
+    # the medium network's front is sizeable: it is where the savings come from
+    fi = acm.Network.from_synth(medium_net).front_info()
+    assert fi["n_front"] > 100 and fi["cost_ratio"] < 0.6
