@@ -192,7 +192,8 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
                o_fcol = p.add(FP.col), o_frs = p.add(FP.rsplit), o_fdg = p.add(FP.vdiag),
                o_fcp = p.add(FP.cptr), o_fcr = p.add(FP.crow), o_fci = p.add(FP.cidx),
                o_fcs = p.add(FP.csplit), o_fasm = p.add(FP.asm_dst), o_ftp = p.add(FP.tg_ptr),
-               o_ftg = p.add(FP.tgt), o_fop = p.add(FP.op_ptr), o_fops = p.add(FP.ops);
+               o_ftg = p.add(FP.tgt), o_fop = p.add(FP.op_ptr), o_fops = p.add(FP.ops),
+               o_fgs = p.add(FP.gseg), o_fgp = p.add(FP.gpc);
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();
@@ -267,6 +268,9 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
   f.tgt = at<int32_t>(b, o_ftg);
   f.op_ptr = at<int32_t>(b, o_fop);
   f.ops = at<int2>(b, o_fops);
+  f.gseg = at<int32_t>(b, o_fgs);
+  f.gpc = at<int2>(b, o_fgp);
+  for (int g = 0; g < 5; ++g) f.gbase[g] = FP.gbase[g];
   *out = net;
   return AC_OK;
 }

@@ -12,41 +12,68 @@
 
 namespace ac {
 
-// acc + sum_{q in [b, e)} sgn * V[q] x[col[q]], four loads in flight.
-template <bool NEG>
-__device__ __forceinline__ double sp_dot_rows(const double *__restrict__ V,
-                                              const int32_t *__restrict__ col,
-                                              const double *x, int b, int e, double acc) {
+// sum_{q in [b, e)} V[q] x[col[q]] (rows) or V[idx[q]] x[row[q]]
+// (columns), eight entries' loads in flight.
+__device__ __forceinline__ double dot_rows(const double *__restrict__ V,
+                                           const int32_t *__restrict__ col, const double *x,
+                                           int b, int e) {
+  double acc = 0.0;
   int q = b;
-  for (; q + 4 <= e; q += 4) {
-    const int c0 = col[q], c1 = col[q + 1], c2 = col[q + 2], c3 = col[q + 3];
-    const double v0 = V[q], v1 = V[q + 1], v2 = V[q + 2], v3 = V[q + 3];
-    acc = fma(NEG ? -v0 : v0, x[c0], acc);
-    acc = fma(NEG ? -v1 : v1, x[c1], acc);
-    acc = fma(NEG ? -v2 : v2, x[c2], acc);
-    acc = fma(NEG ? -v3 : v3, x[c3], acc);
+  for (; q + 8 <= e; q += 8) {
+    int c[8];
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      c[u] = col[q + u];
+      v[u] = V[q + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fma(v[u], x[c[u]], acc);
   }
-  for (; q < e; ++q) acc = fma(NEG ? -V[q] : V[q], x[col[q]], acc);
+  for (; q < e; ++q) acc = fma(V[q], x[col[q]], acc);
   return acc;
 }
 
-// acc + sum_{q in [b, e)} sgn * V[idx[q]] x[row[q]] (column order).
-template <bool NEG>
-__device__ __forceinline__ double sp_dot_cols(const double *__restrict__ V,
-                                              const int32_t *__restrict__ idx,
-                                              const int32_t *__restrict__ row, const double *x,
-                                              int b, int e, double acc) {
+__device__ __forceinline__ double dot_cols(const double *__restrict__ V,
+                                           const int32_t *__restrict__ idx,
+                                           const int32_t *__restrict__ row, const double *x,
+                                           int b, int e) {
+  double acc = 0.0;
   int q = b;
-  for (; q + 4 <= e; q += 4) {
-    const int i0 = idx[q], i1 = idx[q + 1], i2 = idx[q + 2], i3 = idx[q + 3];
-    const int r0 = row[q], r1 = row[q + 1], r2 = row[q + 2], r3 = row[q + 3];
-    const double v0 = V[i0], v1 = V[i1], v2 = V[i2], v3 = V[i3];
-    acc = fma(NEG ? -v0 : v0, x[r0], acc);
-    acc = fma(NEG ? -v1 : v1, x[r1], acc);
-    acc = fma(NEG ? -v2 : v2, x[r2], acc);
-    acc = fma(NEG ? -v3 : v3, x[r3], acc);
+  for (; q + 8 <= e; q += 8) {
+    int i[8], r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      i[u] = idx[q + u];
+      r[u] = row[q + u];
+    }
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = V[i[u]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fma(v[u], x[r[u]], acc);
   }
-  for (; q < e; ++q) acc = fma(NEG ? -V[idx[q]] : V[idx[q]], x[row[q]], acc);
+  for (; q < e; ++q) acc = fma(V[idx[q]], x[row[q]], acc);
+  return acc;
+}
+
+// Partial sums of gather g's pieces (plan: frontlu.h) into part (LDS).
+template <int NT, bool COLS>
+__device__ __forceinline__ void gather_pieces(const DFront &F, int g, const double *V,
+                                              const double *x, double *part) {
+  const int p0 = F.gbase[g], p1 = F.gbase[g + 1];
+  for (int p = p0 + int(threadIdx.x); p < p1; p += NT) {
+    const int2 r = F.gpc[p];
+    part[p - p0] = COLS ? dot_cols(V, F.cidx, F.crow, x, r.x, r.y) : dot_rows(V, F.col, x, r.x, r.y);
+  }
+}
+
+// Sum of output r's pieces of gather g, in piece order.
+__device__ __forceinline__ double gather_sum(const DFront &F, int g, int r, const double *part) {
+  const int32_t *seg = F.gseg + size_t(g) * (F.n + 1);
+  const int p0 = F.gbase[g];
+  double acc = 0.0;
+  for (int p = seg[r]; p < seg[r + 1]; ++p) acc += part[p - p0];
   return acc;
 }
 
@@ -98,7 +125,17 @@ __device__ __forceinline__ int front_factor(const DNet &n, const double *__restr
       const double p = V[d];
       if (p == 0.0) atomicMin(&redi[0], k);
       const double inv = 1.0 / p;
-      for (int q = F.row_ptr[k]; q < F.row_ptr[k + 1]; ++q)
+      int q = F.row_ptr[k];
+      const int qe = F.row_ptr[k + 1];
+      for (; q + 8 <= qe; q += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = V[q + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (q + u != d) V[q + u] = v[u] * inv;
+      }
+      for (; q < qe; ++q)
         if (q != d) V[q] *= inv;
     }
     __syncthreads();
@@ -107,7 +144,22 @@ __device__ __forceinline__ int front_factor(const DNet &n, const double *__restr
       const int d = F.tgt[t];
       double *dst = d >= 0 ? V + d : S + (-1 - d);
       double a = *dst;
-      for (int o = F.op_ptr[t]; o < F.op_ptr[t + 1]; ++o) {
+      int o = F.op_ptr[t];
+      const int oe = F.op_ptr[t + 1];
+      for (; o + 8 <= oe; o += 8) {
+        int2 op[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) op[u] = F.ops[o + u];
+        double l[8], r[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          l[u] = V[op[u].x];
+          r[u] = V[op[u].y];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a = fma(-l[u], r[u], a);
+      }
+      for (; o < oe; ++o) {
         const int2 op = F.ops[o];
         a = fma(-V[op.x], V[op.y], a);
       }
@@ -118,7 +170,20 @@ __device__ __forceinline__ int front_factor(const DNet &n, const double *__restr
     for (int k = k0 + int(threadIdx.x); k < k1; k += NT) {
       const int d = F.vdiag[k];
       const double inv = 1.0 / V[d];
-      for (int q = F.cptr[k]; q < F.cptr[k + 1]; ++q) {
+      int q = F.cptr[k];
+      const int qe = F.cptr[k + 1];
+      for (; q + 8 <= qe; q += 8) {
+        int vi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) vi[u] = F.cidx[q + u];
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = V[vi[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (vi[u] != d) V[vi[u]] = -v[u] * inv;
+      }
+      for (; q < qe; ++q) {
         const int vi = F.cidx[q];
         if (vi != d) V[vi] = -V[vi] * inv;
       }
@@ -138,7 +203,9 @@ __device__ __forceinline__ int front_factor(const DNet &n, const double *__restr
 
 // Solves M x = b (trans = false) or M^T x = b with the factors of
 // front_factor: x (LDS, natural order) holds b on entry and x on return;
-// tmp (LDS, n doubles) is scratch; blk: the dense solves' LDS blocks.
+// tmp (LDS, n doubles) is scratch; blk (LDS) holds the dense solves' blocks
+// and, before and after them, the gathers' partial sums (at most
+// FRONT_MAX_PIECES doubles).
 template <int NT>
 __device__ __forceinline__ void front_solve(const DFront &F, const double *M, const int *perm2,
                                             double *x, double *tmp, bool trans, double *blk) {
@@ -147,29 +214,30 @@ __device__ __forceinline__ void front_solve(const DFront &F, const double *M, co
   for (int i = threadIdx.x; i < n; i += NT) tmp[i] = x[F.perm[i]];
   __syncthreads();
   if (!trans) {
-    // front: A^-1 b1; tail: b2 - C A^-1 b1 (positions, into x)
-    for (int r = threadIdx.x; r < n; r += NT) {
-      const bool fr = r < n1;
-      x[r] = sp_dot_rows<false>(V, F.col, tmp, F.row_ptr[r], fr ? F.rsplit[r] : F.row_ptr[r + 1],
-                                fr ? 0.0 : tmp[r]);
-    }
+    // front: A^-1 b1; tail: b2 - C A^-1 b1 (the stored values are -C A^-1)
+    gather_pieces<NT, false>(F, 0, V, tmp, blk);
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += NT) x[r] = (r < n1 ? 0.0 : tmp[r]) + gather_sum(F, 0, r, blk);
     __syncthreads();
     if (n2 > 0) wg_solve<NT>(S, F.lda2, n2, perm2, x + n1, tmp + n1, false, blk);
     // front: z1 = A^-1 b1 - A^-1 B z2
-    for (int r = threadIdx.x; r < n; r += NT)
-      tmp[r] = r < n1 ? sp_dot_rows<true>(V, F.col, x, F.rsplit[r], F.row_ptr[r + 1], x[r]) : x[r];
+    gather_pieces<NT, false>(F, 1, V, x, blk);
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += NT) tmp[r] = x[r] - gather_sum(F, 1, r, blk);
   } else {
     // front: A^-T b1; tail: b2 - (A^-1 B)^T b1
+    gather_pieces<NT, true>(F, 2, V, tmp, blk);
+    __syncthreads();
     for (int q = threadIdx.x; q < n; q += NT) {
-      if (q < n1) x[q] = sp_dot_cols<false>(V, F.cidx, F.crow, tmp, F.cptr[q], F.csplit[q], 0.0);
-      else x[q] = sp_dot_cols<true>(V, F.cidx, F.crow, tmp, F.cptr[q], F.cptr[q + 1], tmp[q]);
+      const double g = gather_sum(F, 2, q, blk);
+      x[q] = q < n1 ? g : tmp[q] - g;
     }
     __syncthreads();
     if (n2 > 0) wg_solve<NT>(S, F.lda2, n2, perm2, x + n1, tmp + n1, true, blk);
-    // front: z1 = A^-T b1 - (C A^-1)^T z2 (the stored values are -C A^-1)
-    for (int q = threadIdx.x; q < n; q += NT)
-      tmp[q] = q < n1 ? sp_dot_cols<false>(V, F.cidx, F.crow, x, F.csplit[q], F.cptr[q + 1], x[q])
-                      : x[q];
+    // front: z1 = A^-T b1 + (-C A^-1)^T z2
+    gather_pieces<NT, true>(F, 3, V, x, blk);
+    __syncthreads();
+    for (int q = threadIdx.x; q < n; q += NT) tmp[q] = x[q] + gather_sum(F, 3, q, blk);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += NT) x[F.perm[i]] = tmp[i];

@@ -33,6 +33,9 @@ struct DFront {
   const int32_t *perm, *lev_ptr, *row_ptr, *col, *rsplit, *vdiag, *cptr, *crow, *cidx, *csplit;
   const int32_t *asm_dst, *tg_ptr, *tgt, *op_ptr;
   const int2 *ops;
+  const int32_t *gseg;   // [4 (n + 1)] pieces of each output of the solves' four gathers
+  const int2 *gpc;       // entry range of every piece
+  int gbase[5];          // first piece of each gather
 };
 
 struct DNet {

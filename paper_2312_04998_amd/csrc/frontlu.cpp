@@ -131,7 +131,10 @@ FrontPlan build_front_plan(int n, const std::vector<int32_t> &j_row_ptr,
       }
       const int n2 = n - k;
       const double cst = model_cost(n2, nv, ops);
-      const bool fits = size_t(vofs_of(n2)) + size_t(nv) <= max_doubles && nv < INT_MAX / 2;
+      // the values fit the slot's region, and every gather's pieces (at most
+      // nv / FRONT_PIECE + n) fit the solves' LDS block
+      const bool fits = size_t(vofs_of(n2)) + size_t(nv) <= max_doubles &&
+                        nv / FRONT_PIECE + n <= FRONT_MAX_PIECES;
       if (k == 0) {
         best = cst;
         F.cost_dense = cst;
@@ -248,6 +251,28 @@ FrontPlan build_front_plan(int n, const std::vector<int32_t> &j_row_ptr,
   F.asm_dst.resize(j_col.size());
   for (int r = 0; r < n; ++r)
     for (int e = j_row_ptr[r]; e < j_row_ptr[r + 1]; ++e) F.asm_dst[e] = code(pos[r], pos[j_col[e]]);
+
+  // Pieces of the solves' four sparse products.
+  F.gseg.assign(size_t(4) * (n + 1), 0);
+  for (int g = 0; g < 4; ++g) {
+    F.gbase[g] = int(F.gpc.size() / 2);
+    int32_t *seg = &F.gseg[size_t(g) * (n + 1)];
+    seg[0] = F.gbase[g];
+    for (int r = 0; r < n; ++r) {
+      int b = 0, e = 0;
+      const bool fr = r < n1;
+      if (g == 0) { b = F.row_ptr[r]; e = fr ? F.rsplit[r] : F.row_ptr[r + 1]; }
+      if (g == 1 && fr) { b = F.rsplit[r]; e = F.row_ptr[r + 1]; }
+      if (g == 2) { b = F.cptr[r]; e = fr ? F.csplit[r] : F.cptr[r + 1]; }
+      if (g == 3 && fr) { b = F.csplit[r]; e = F.cptr[r + 1]; }
+      for (int q = b; q < e; q += FRONT_PIECE) {
+        F.gpc.push_back(q);
+        F.gpc.push_back(std::min(e, q + FRONT_PIECE));
+      }
+      seg[r + 1] = int(F.gpc.size() / 2);
+    }
+  }
+  F.gbase[4] = int(F.gpc.size() / 2);
 
   // Per level: targets, most products first; products in sweep order.
   F.tg_ptr.push_back(0);

@@ -57,8 +57,22 @@ struct FrontPlan {
   std::vector<int32_t> tgt;       // [n_tgt]
   std::vector<int32_t> op_ptr;    // [n_tgt + 1]
   std::vector<int32_t> ops;       // [2 n_op] pairs
+  // The solves' four sparse products (forward before / after the dense
+  // solve: rows over [row_ptr, rsplit) or the whole tail row, then front
+  // rows over [rsplit, row_ptr+1); transposed: the same by column) cut into
+  // pieces of at most FRONT_PIECE entries, so that long rows are summed by
+  // several threads. Gather g: output position r owns pieces
+  // gseg[g*(n+1) + r] .. gseg[g*(n+1) + r + 1] - 1; piece p covers entries
+  // [gpc[2p], gpc[2p+1]) (CSR entries for the row gathers 0, 1, CSC
+  // entries for the column gathers 2, 3); gbase[g] is its first piece.
+  std::vector<int32_t> gseg;      // [4 (n + 1)]
+  std::vector<int32_t> gpc;       // [2 n_piece]
+  int gbase[5] = {0, 0, 0, 0, 0};
   double cost_front = 0.0, cost_dense = 0.0;   // modelled seconds per factorisation
 };
+
+constexpr int FRONT_PIECE = 16;
+constexpr int FRONT_MAX_PIECES = 8192;   // partial sums per gather (doubles of LDS)
 
 // Builds the plan for an n x n Jacobian pattern (CSR, natural order) whose
 // Newton matrix region holds max_doubles doubles per slot.
