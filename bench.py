@@ -379,6 +379,19 @@ def integration_legs(args, torch, acm, net):
           f"{'cached' if slots_cached else 'tuned'})", file=sys.stderr, flush=True)
     N = acm.Network.from_synth(net)
     ws = acm.Workspace(N, n_slots=slots)
+    # the Newton solve on the same sample: the plan (minimum-degree front swept
+    # sparsely, dense Schur tail) against one pivoted LU of the whole matrix
+    solve_rate = {}
+    for solver in ("dense", "auto", "dense", "auto"):
+        yy = y[:m].clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        oo = ws.integrate(yy, T[:m], t_end, max_steps=200, linear_solver=solver)
+        torch.cuda.synchronize()
+        solve_rate[solver] = float(oo["stats"][:, 0].sum().item()) / (time.perf_counter() - t0)
+    plan = {k: v for k, v in N.front_info().items() if k != "order"}
+    print(f"[bench] Newton solve: steps/s {solve_rate} (front {plan['n_front']} species in "
+          f"{plan['n_levels']} levels)", file=sys.stderr, flush=True)
     # cells expected to take longest first: step counts grow with density
     order = torch.from_numpy(np.argsort(-cells.n_H, kind="stable").astype(np.int32)).to(dev)
     wall, st, status = _integrate_watched(torch, ws, y, T, t_end, K,
@@ -399,15 +412,15 @@ def integration_legs(args, torch, acm, net):
     sb = ob["stats"].cpu().numpy()
     wall_p, sp, stp, same = 0.0, [], [], True
     for k in range(0, npl, 8):
-        yp = torch.from_numpy(cells.y0[k:k + 8].copy()).to(dev)
+        yp = torch.from_numpy(cells.y0[k:min(k + 8, npl)].copy()).to(dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        op = ws.integrate(yp, Tp[k:k + 8], t_end, max_steps=Kp, plain=True)
+        op = ws.integrate(yp, Tp[k:min(k + 8, npl)], t_end, max_steps=Kp, plain=True)
         torch.cuda.synchronize()
         wall_p += time.perf_counter() - t0
         sp.append(op["stats"].cpu().numpy())
         stp.append(op["status"].cpu().numpy())
-        same = same and bool(torch.equal(yp, yb[k:k + 8]))
+        same = same and bool(torch.equal(yp, yb[k:min(k + 8, npl)]))
         print(f"[bench] plain loop: {min(k + 8, npl)}/{npl} cells, {wall_p:.1f} s", file=sys.stderr,
               flush=True)
     sp, stp = np.concatenate(sp), np.concatenate(stp)
@@ -430,6 +443,10 @@ def integration_legs(args, torch, acm, net):
                       "not depend on the order",
         "slot_tuning": {"steps_per_s_by_slots": slot_rate, "from_cache": slots_cached,
                         "sample": f"first {m} cells, 200 steps each"},
+        "newton_solve": {"used": "auto", "plan": plan, "steps_per_s": solve_rate,
+                         "auto_over_dense": solve_rate["auto"] / solve_rate["dense"],
+                         "sample": f"first {m} cells, 200 steps each, {ws.n_slots} slots; "
+                                   "second of two runs each"},
         "plain": {"cells": npl, "max_steps": Kp, "wall_s": wall_p, "cells_reaching_t_end": ok_p,
                   "steps": int(sp[:, 0].sum()), "steps_per_s": float(sp[:, 0].sum() / wall_p),
                   "batched_wall_s_same_cells": wall_b,

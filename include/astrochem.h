@@ -176,7 +176,9 @@ ac_status ac_net_row_order(const ac_net *net, int32_t *perm /*n_species*/);
  * cost of a factorisation and its solves relative to one dense LU of the
  * whole matrix (< 1 means the plan is expected to be faster). The front is
  * chosen by the minimum-degree order of the pattern, as in the sparse solve
- * of DLSODES (Sec. 3). Any output may be NULL. */
+ * of DLSODES (Sec. 3). n_front = 0: the front would not repay its fixed
+ * latency (small networks), and AUTO factors the whole matrix densely. Any
+ * output may be NULL. */
 ac_status ac_net_front_info(const ac_net *net, int32_t *n_front, int32_t *n_levels,
                             int64_t *n_values, int64_t *n_updates, double *cost_ratio,
                             int32_t *order /*n_species*/);

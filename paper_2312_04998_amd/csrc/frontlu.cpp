@@ -98,8 +98,49 @@ double model_cost(int n2, long long nv, long long ops) {
   return 28.0 * solve_bytes / 2.8e12 + (2.0 / 3.0) * double(n2) * n2 * n2 / 7.8e12 + double(ops) * 2e-11;
 }
 
+// The front's fixed latency per factorisation cycle, in the same chip time:
+// each solve adds about six dependent rounds (permutations, two gathers
+// and their sums, about 1 us each), each sweep level three; a workgroup
+// waits for them alone, so they cost the chip 1/64 of that time (a
+// quarter of the slots in that state at once).
+double front_overhead(int n_lev) {
+  return (28.0 * 6.0 + 3.0 * n_lev + 4.0) * 1e-6 / 64.0;
+}
+
 int round16(int x) { return (x + 15) / 16 * 16; }
 int vofs_of(int n2) { return (n2 * round16(n2) + 31) / 32 * 32; }
+
+// Greedy levels of the first n1 pivots of the minimum-degree order:
+// lev_ptr (starting {0}) gets the level boundaries, order the md
+// positions in sweep order.
+void front_order_of(int n, const std::vector<int32_t> &j_row_ptr, const std::vector<int32_t> &j_col,
+                    const std::vector<int> &md_pos, int n1, std::vector<int32_t> &lev_ptr,
+                    std::vector<int> &front_order) {
+  front_order.clear();
+  BitMat Fm = permuted_pattern(n, j_row_ptr, j_col, md_pos);
+  std::vector<char> done(n1, 0);
+  int left = n1;
+  while (left > 0) {
+    std::vector<int> lev;
+    for (int k = 0; k < n1; ++k) {
+      if (done[k]) continue;
+      bool ok = true;
+      for (int m : lev)
+        if (Fm.get(k, m) || Fm.get(m, k)) {
+          ok = false;
+          break;
+        }
+      if (ok) lev.push_back(k);
+    }
+    for (int k : lev) {
+      Fm.sweep(k, nullptr);
+      done[k] = 1;
+      front_order.push_back(k);
+    }
+    left -= int(lev.size());
+    lev_ptr.push_back(int(front_order.size()));
+  }
+}
 
 }  // namespace
 
@@ -150,36 +191,20 @@ FrontPlan build_front_plan(int n, const std::vector<int32_t> &j_row_ptr,
   }
 
   // Levels: greedy maximal sets of front pivots that share no entry, in
-  // minimum-degree order, each set swept before the next is chosen.
-  const int n1 = best_n1;
+  // minimum-degree order, each set swept before the next is chosen. A
+  // front that does not save more than its fixed latency is dropped (n1 =
+  // 0: the whole matrix is factored densely).
+  int n1 = best_n1;
   std::vector<int> front_order;   // md positions in sweep order
-  F.lev_ptr.push_back(0);
-  {
-    BitMat Fm = permuted_pattern(n, j_row_ptr, j_col, md_pos);
-    std::vector<char> done(n1, 0);
-    int left = n1;
-    while (left > 0) {
-      std::vector<int> lev;
-      std::vector<char> in(n, 0);
-      for (int k = 0; k < n1; ++k) {
-        if (done[k]) continue;
-        bool ok = true;
-        for (int m : lev)
-          if (Fm.get(k, m) || Fm.get(m, k)) {
-            ok = false;
-            break;
-          }
-        if (ok) lev.push_back(k);
-      }
-      for (int k : lev) {
-        Fm.sweep(k, nullptr);
-        done[k] = 1;
-        front_order.push_back(k);
-      }
-      left -= int(lev.size());
-      F.lev_ptr.push_back(int(front_order.size()));
-    }
+  for (;;) {
+    F.lev_ptr.assign(1, 0);
+    front_order_of(n, j_row_ptr, j_col, md_pos, n1, F.lev_ptr, front_order);
+    const int n_lev = int(F.lev_ptr.size()) - 1;
+    if (n1 == 0 || F.cost_front + front_overhead(n_lev) < F.cost_dense) break;
+    n1 = 0;
+    F.cost_front = F.cost_dense;
   }
+  if (n1 > 0) F.cost_front += front_overhead(int(F.lev_ptr.size()) - 1);
   F.n1 = n1;
   F.n2 = n - n1;
   F.n_lev = int(F.lev_ptr.size()) - 1;

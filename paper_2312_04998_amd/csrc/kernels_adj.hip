@@ -206,7 +206,7 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
   cx.red = red;
   cx.redi = redi;
   cx.ipiv = ipiv;
-  cx.front = P.linear_solver == AC_LINSOLVE_AUTO && n.fr.n == n.ns;
+  cx.front = P.linear_solver == AC_LINSOLVE_AUTO && n.fr.n == n.ns && n.fr.n1 > 0;
   double *Db = A.Db + slot * A.db_stride;
   double *ck = A.ck + slot * A.ck_stride;
   int *ckev = A.ckev + slot * A.ckev_stride;

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
   cx.nc = n.n_cond;
   cx.la_over = la_over;
   cx.Jaux = cx.Jg + n.nnz_j;
-  cx.front = !TH && P.linear_solver == AC_LINSOLVE_AUTO && n.fr.n == n.ns;
+  cx.front = !TH && P.linear_solver == AC_LINSOLVE_AUTO && n.fr.n == n.ns && n.fr.n1 > 0;
   const double rtol = P.rtol, atol = P.atol, t_end = P.t_end;
   const double tol = P.newton_tol > 0.0
                          ? P.newton_tol

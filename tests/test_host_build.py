@@ -250,17 +250,18 @@ def test_front_plan(acm, medium_net, tiny):
     """The integrator's Newton-solve plan: a permutation of the species with
     the front first, starting at a species of least degree in the symmetric
     pattern of I - c J (minimum degree, ties to the smaller index), a front
-    strictly between empty and everything on the paper-sized network, every
-    pattern entry of a front row or column among the stored sparse values,
-    and a modelled cost below one dense LU."""
+    strictly between empty and everything on the paper-sized network (none
+    on the 50-species network, where it would not repay its fixed latency),
+    every pattern entry of a front row or column among the stored sparse
+    values, and a modelled cost below one dense LU."""
     for net in (medium_net, tiny[0]):
         N = acm.Network.from_synth(net)
         fi = N.front_info()
         ns = N.n_species
         order = fi["order"]
         assert sorted(order.tolist()) == list(range(ns))
-        assert 0 < fi["n_front"] < ns and fi["n_levels"] >= 1
-        assert fi["cost_ratio"] < 1.0
+        assert 0 <= fi["n_front"] < ns and fi["cost_ratio"] <= 1.0
+        assert (fi["n_levels"] >= 1) == (fi["n_front"] > 0)
         rp, col = N.jac_pattern()
         rows = np.repeat(np.arange(ns), np.diff(rp))
         P = sp.coo_matrix((np.ones(len(col)), (rows, col)), shape=(ns, ns)).tocsr()
@@ -276,3 +277,4 @@ def test_front_plan(acm, medium_net, tiny):
     # the medium network's front is sizeable: it is where the savings come from
     fi = acm.Network.from_synth(medium_net).front_info()
     assert fi["n_front"] > 100 and fi["cost_ratio"] < 0.6
+    assert acm.Network.from_synth(tiny[0]).front_info()["n_front"] == 0
