@@ -77,6 +77,11 @@ struct AdjIO {
 };
 
 size_t bdf_lds_bytes(const DNet &n);
+// Whether the integrator and the adjoint factor with the sparse front (the
+// plan has one and the options ask for AUTO); selects the kernel instance.
+inline bool use_front(const DNet &n, const BdfParams &P) {
+  return P.linear_solver == AC_LINSOLVE_AUTO && n.fr.n == n.ns && n.fr.n1 > 0;
+}
 int bdf_resident_blocks(const DNet &n);
 // therm non-null selects the temperature-coupled mode (state ns + 1 per
 // cell, therm [n_cells][3] = (c_v, T_b, lambda)).

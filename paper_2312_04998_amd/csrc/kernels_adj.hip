@@ -175,7 +175,7 @@ __device__ __forceinline__ void reverse_step(CellCtx &cx, const AdjVecs &v, doub
   __syncthreads();
 }
 
-template <int NT>
+template <int NT, bool FR>
 __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ la_over,
                                             int64_t n_cells, AdjIO io, BdfParams P, WsView W,
                                             AdjView A, unsigned *queue) {
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(NT) void k_adj(DNet n, const double *__restrict__ l
   cx.red = red;
   cx.redi = redi;
   cx.ipiv = ipiv;
-  cx.front = P.linear_solver == AC_LINSOLVE_AUTO && n.fr.n == n.ns && n.fr.n1 > 0;
+  cx.front = FR;
   double *Db = A.Db + slot * A.db_stride;
   double *ck = A.ck + slot * A.ck_stride;
   int *ckev = A.ckev + slot * A.ckev_stride;
@@ -370,13 +370,13 @@ hipError_t launch_adjoint(const DNet &n, const double *la, int64_t n_cells, cons
                           int grid, hipStream_t st) {
   if (n_cells == 0) return hipSuccess;
   const size_t lds = bdf_lds_bytes(n);
-  if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(k_adj<BDF_NT>),
+  auto kern = use_front(n, P) ? k_adj<BDF_NT, true> : k_adj<BDF_NT, false>;
+  if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   hipError_t e = launch_reset_queue(queue, st);
   if (e != hipSuccess) return e;
   const int g = int(n_cells < grid ? n_cells : grid);
-  hipLaunchKernelGGL(k_adj<BDF_NT>, dim3(g), dim3(BDF_NT), lds, st, n, la, n_cells, io, P, W, A,
-                     queue);
+  hipLaunchKernelGGL(kern, dim3(g), dim3(BDF_NT), lds, st, n, la, n_cells, io, P, W, A, queue);
   return hipGetLastError();
 }
 

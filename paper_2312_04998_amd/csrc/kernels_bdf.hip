@@ -43,8 +43,10 @@ __device__ __forceinline__ void tape_put(const TapeView &tv, int64_t cell, int &
 
 // TH: temperature-coupled mode, the state is (n_1..n_ns, T) and therm
 // holds (c_v, T_b, lambda) per cell; otherwise T is held at the cell's
-// conditions. ns below is the length of the state vector.
-template <int NT, bool TH>
+// conditions. ns below is the length of the state vector. FR: the Newton
+// matrix is factored with the sparse front (a separate instance, so that
+// the dense path keeps its own register allocation).
+template <int NT, bool TH, bool FR>
 __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ la_over,
                                             int64_t n_cells, double *__restrict__ y,
                                             const double *__restrict__ T,
@@ -82,7 +84,7 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
   cx.nc = n.n_cond;
   cx.la_over = la_over;
   cx.Jaux = cx.Jg + n.nnz_j;
-  cx.front = !TH && P.linear_solver == AC_LINSOLVE_AUTO && n.fr.n == n.ns && n.fr.n1 > 0;
+  cx.front = FR && !TH;
   const double rtol = P.rtol, atol = P.atol, t_end = P.t_end;
   const double tol = P.newton_tol > 0.0
                          ? P.newton_tol
@@ -396,10 +398,10 @@ size_t bdf_lds_bytes(const DNet &n) {
 
 int bdf_resident_blocks(const DNet &n) {
   const size_t lds = bdf_lds_bytes(n);
-  if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(k_bdf<BDF_NT, false>),
+  if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(k_bdf<BDF_NT, false, false>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bdf<BDF_NT, false>, BDF_NT, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bdf<BDF_NT, false, false>, BDF_NT, lds) !=
           hipSuccess || per_cu <= 0)
     per_cu = 1;
   int dev = 0, cus = 0;
@@ -414,7 +416,8 @@ hipError_t launch_bdf(const DNet &n, const double *la, int64_t n_cells, double *
                       hipStream_t st) {
   if (n_cells == 0) return hipSuccess;
   const size_t lds = bdf_lds_bytes(n);
-  auto kern = therm ? k_bdf<BDF_NT, true> : k_bdf<BDF_NT, false>;
+  auto kern = therm ? k_bdf<BDF_NT, true, false>
+                    : use_front(n, P) ? k_bdf<BDF_NT, false, true> : k_bdf<BDF_NT, false, false>;
   if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (queue) hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, queue, W.progress);
