@@ -434,6 +434,20 @@ ac_status ac_integrate_thermal(ac_ws *ws, const double *log_alpha, int64_t n_cel
                                const ac_integ_opts *opts, int32_t *cell_status,
                                int32_t *cell_stats, ac_stream stream);
 
+/* The integrator's Newton systems on their own (the corrector of the BDF
+ * code DLSODES, Sec. 3): for matrix m, M = I - c[m] J_m with J_m given by
+ * its values on the network's Jacobian pattern, solves M x = b (trans = 0)
+ * or M^T x = b (trans = 1). jvals: DEVICE [n_mat][nnz_j] (ac_jac's layout);
+ * c: DEVICE [n_mat]; b: DEVICE [n_mat][n_species], overwritten by x; info:
+ * DEVICE [n_mat] or NULL, 0 or 1 + the position of an exactly zero pivot
+ * (x is then not finite). linear_solver as ac_integ_opts.linear_solver. The
+ * workspace's slots hold the factors, one matrix per slot at a time, so
+ * calls on one workspace must not overlap with each other or with an
+ * integration. */
+ac_status ac_newton_solve(ac_ws *ws, int64_t n_mat, const double *jvals, const double *c,
+                          double *b, int32_t trans, int32_t linear_solver, int32_t *info,
+                          ac_stream stream);
+
 /* Same integrator, one cell per kernel launch, one workgroup, launches
  * issued back to back from the host: the unbatched baseline. */
 ac_status ac_integrate_plain(ac_ws *ws, const double *log_alpha, int64_t n_cells, double *y,

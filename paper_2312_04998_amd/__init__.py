@@ -97,6 +97,7 @@ def _load() -> C.CDLL:
         "ac_replay": [vp, vp, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp],
         "ac_integrate_thermal": [vp, vp, i64, vp, vp, vp, d, vp, vp, vp, vp],
         "ac_ws_reserve_adjoint": [vp, vp],
+        "ac_newton_solve": [vp, i64, vp, vp, vp, i32, i32, vp, vp],
         "ac_ws_adjoint_info": [vp, vp, vp, vp, vp],
     }
     for name, args in sig2.items():
@@ -480,6 +481,22 @@ class Workspace:
         if tape_cap > self.adj_max_tape or every != self.checkpoint_every:
             self.reserve_adjoint(max(tape_cap, self.adj_max_tape if every == self.checkpoint_every
                                      else 0), every, self.keep_states, self.adj_max_cells)
+
+    def newton_solve(self, jvals, c, b, trans=False, linear_solver="auto", stream=None):
+        """Solves (I - c[m] J_m) x = b[m] (or the transposed system) in place
+        in b [n_mat, ns] for Jacobian pattern values jvals [n_mat, nnz_j] and
+        c [n_mat] (device float64), with the integrator's Newton solve;
+        returns info [n_mat] (0, or 1 + a zero pivot's position)."""
+        import torch
+        n = b.shape[0]
+        _check_dev(b, (n, self.net.n_species), "b")
+        _check_dev(jvals, (n, self.net.nnz_j), "jvals")
+        _check_dev(c, (n,), "c")
+        info = torch.empty(n, dtype=torch.int32, device=b.device)
+        check(lib.ac_newton_solve(self.handle, n, _ptr(jvals), _ptr(c), _ptr(b), 1 if trans else 0,
+                                  _solver(linear_solver), _ptr(info), _stream(stream)),
+              "ac_newton_solve")
+        return info
 
     def progress(self) -> int:
         """ac_ws_progress: cells taken so far by the running (or last)

@@ -738,6 +738,23 @@ ac_status ac_integrate_plain(ac_ws *ws, const double *log_alpha, int64_t n_cells
   return AC_OK;
 }
 
+ac_status ac_newton_solve(ac_ws *ws, int64_t n_mat, const double *jvals, const double *c,
+                          double *b, int32_t trans, int32_t linear_solver, int32_t *info,
+                          ac_stream stream) {
+  if (!ws) return fail(AC_EINVAL, "null workspace");
+  if (n_mat < 0) return fail(AC_EINVAL, "n_mat < 0");
+  if (n_mat && (!jvals || !c || !b)) return fail(AC_EINVAL, "null jvals, c or b");
+  if (trans != 0 && trans != 1) return fail(AC_EINVAL, "trans must be 0 or 1");
+  if (linear_solver != AC_LINSOLVE_AUTO && linear_solver != AC_LINSOLVE_DENSE)
+    return fail(AC_EINVAL, "linear_solver must be AC_LINSOLVE_AUTO or AC_LINSOLVE_DENSE");
+  ac::BdfParams P{};
+  P.linear_solver = linear_solver;
+  hipError_t e = ac::launch_newton(ws->net->d, n_mat, jvals, c, b, trans,
+                                   ac::use_front(ws->net->d, P), ws->W, ws->n_slots, info,
+                                   hipStream_t(stream));
+  return e == hipSuccess ? AC_OK : hip_fail(e, "ac_newton_solve launch");
+}
+
 // Adjoint slots for tapes of up to max_tape events: a checkpoint store
 // (max_tape / every + 1 difference arrays), the converged states of one
 // segment or, with keep_states and when they fit the budget over all

@@ -90,6 +90,12 @@ hipError_t launch_bdf(const DNet &n, const double *la, int64_t n_cells, double *
                       const TapeView &tv, const WsView &W, unsigned *queue, int grid,
                       hipStream_t st);
 hipError_t launch_reset_queue(unsigned *queue, hipStream_t st);
+// Newton systems (I - c J) x = b (or transposed) with the integrator's
+// factorisation, one matrix per workspace slot at a time; info [n_mat] or
+// null gets 0 or 1 + a zero pivot's position.
+hipError_t launch_newton(const DNet &n, int64_t n_mat, const double *jvals, const double *c,
+                         double *b, int trans, bool front, const WsView &W, int slots,
+                         int32_t *info, hipStream_t st);
 hipError_t launch_adjoint(const DNet &n, const double *la, int64_t n_cells, const AdjIO &io,
                           const BdfParams &P, const WsView &W, const AdjView &A, unsigned *queue,
                           int grid, hipStream_t st);

@@ -337,6 +337,58 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
   }
 }
 
+// The integrator's Newton systems on their own: matrix m is I - c[m] J_m
+// with J_m's pattern values at jvals + m nnz_j; b [n_mat][ns] is solved in
+// place, plainly or transposed. Workgroup g uses slot g and takes the
+// matrices g, g + grid, ...
+template <int NT, bool FR>
+__global__ __launch_bounds__(NT) void k_newton(DNet n, int64_t n_mat, const double *__restrict__ jvals,
+                                               const double *__restrict__ c, double *__restrict__ b,
+                                               int trans, WsView W, int32_t *__restrict__ info) {
+  extern __shared__ double sm[];
+  const int ns = n.ns;
+  double *x = sm, *tmp = x + ns, *scr = tmp + ns;
+  double *red = scr + bdf_scratch_doubles(n);
+  int *redi = reinterpret_cast<int *>(red + 16 + 3 * (QMAX + 1) * (QMAX + 1));
+  int *ipiv = redi + 16;
+  const size_t slot = blockIdx.x;
+  CellCtx cx;
+  cx.n = &n;
+  cx.M = W.M + slot * W.m_stride;
+  cx.piv = W.piv + slot * W.piv_stride;
+  cx.perm = cx.piv + ns;
+  cx.lda = W.lda;
+  cx.scr = scr;
+  cx.tmp = tmp;
+  cx.red = red;
+  cx.redi = redi;
+  cx.ipiv = ipiv;
+  cx.front = FR;
+  for (int64_t m = blockIdx.x; m < n_mat; m += gridDim.x) {
+    cx.Jg = const_cast<double *>(jvals) + m * n.nnz_j;
+    cell_factor<NT>(cx, c[m]);
+    for (int i = threadIdx.x; i < ns; i += NT) x[i] = b[m * ns + i];
+    __syncthreads();
+    cell_solve<NT, false>(cx, x, trans != 0);
+    for (int i = threadIdx.x; i < ns; i += NT) b[m * ns + i] = x[i];
+    if (threadIdx.x == 0 && info) info[m] = cx.lu_info;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_newton(const DNet &n, int64_t n_mat, const double *jvals, const double *c,
+                         double *b, int trans, bool front, const WsView &W, int slots,
+                         int32_t *info, hipStream_t st) {
+  if (n_mat == 0) return hipSuccess;
+  const size_t lds = bdf_lds_bytes(n);
+  auto kern = front ? k_newton<BDF_NT, true> : k_newton<BDF_NT, false>;
+  if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  const int g = int(n_mat < slots ? n_mat : slots);
+  hipLaunchKernelGGL(kern, dim3(g), dim3(BDF_NT), lds, st, n, n_mat, jvals, c, b, trans, W, info);
+  return hipGetLastError();
+}
+
 __global__ void k_reset_queue(unsigned *q, unsigned *progress) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     *q = 0u;

@@ -372,3 +372,47 @@ def test_recorded_tape_matches_oracle(acm, torch_dev, oracle_mod, tiny, medium_n
         assert g[3] <= max(3 * p[:, 3].max(), 1e-3)
         # the first event (the initial step size) is rounding-stable
         np.testing.assert_allclose(tape[c]["val"][:1], ref["tape"][c]["val"][:1], rtol=1e-9)
+
+
+@pytest.mark.parametrize("solver", ["auto", "dense"])
+def test_newton_solve_backward_error(acm, torch_dev, oracle_mod, medium, solver):
+    """The integrator's Newton solve on its own (ac_newton_solve), on the
+    oracle's Jacobians of five cells of the paper-sized network at c from
+    1e-2 to 3e13 s, plain and transposed, five matrices over four slots (a
+    slot factors twice): the normwise backward error against the same
+    matrices, |M x - b|_2 / (|M|_1 |x|_1 + |b|_1), stays below 1e-14 (CPU
+    studies of both algorithms give at most 5e-18; the matrix itself is
+    rounded differently, I - cJ in one fused step on the GPU) for the
+    sparse front with its dense tail (auto) and for one pivoted LU (dense),
+    and the solution agrees with numpy where M is well conditioned."""
+    torch = torch_dev
+    net, cells = medium
+    N = acm.Network.from_synth(net)
+    ws = acm.Workspace(N, n_slots=4)
+    idx = [0, 3, 7, 11, 13]
+    cs = np.array([1e-2, 1e3, 1e7, 1e11, 3e13])
+    J = oracle_mod.jac_dense(net, cells.y0[idx], cells.T[idx])
+    rp, col = N.jac_pattern()
+    rows = np.repeat(np.arange(N.n_species), np.diff(rp))
+    jv = _t(torch, J[:, rows, col])
+    b = np.random.default_rng(17).standard_normal((len(idx), N.n_species))
+    for trans in (False, True):
+        x = _t(torch, b)
+        info = ws.newton_solve(jv, _t(torch, cs), x, trans=trans, linear_solver=solver)
+        assert info.cpu().tolist() == [0] * len(idx)
+        x = x.cpu().numpy()
+        for m in range(len(idx)):
+            A = np.eye(N.n_species) - cs[m] * J[m]
+            A = A.T if trans else A
+            be = np.linalg.norm(A @ x[m] - b[m]) / (np.abs(A).sum(0).max() * np.abs(x[m]).sum()
+                                                    + np.abs(b[m]).sum())
+            assert be < 1e-14, (trans, m, be)
+            if cs[m] <= 1e7:
+                ref = np.linalg.solve(A, b[m])
+                np.testing.assert_allclose(x[m], ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+    # empty batch and bad shapes
+    e = torch.empty((0, N.n_species), dtype=torch.float64, device="cuda")
+    ws.newton_solve(torch.empty((0, N.nnz_j), dtype=torch.float64, device="cuda"),
+                    torch.empty(0, dtype=torch.float64, device="cuda"), e)
+    with pytest.raises(ValueError):
+        ws.newton_solve(jv[:2], _t(torch, cs[:3]), _t(torch, b[:2]))
