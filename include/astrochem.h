@@ -298,7 +298,8 @@ ac_status ac_lu_solve(int32_t n, int32_t lda, int64_t n_mat, const double *LU,
 
 /* ---------------------------------------------------------- integrator
  * Variable-order (1..q_max <= 5) BDF in backward-difference form with a
- * simplified Newton corrector on the dense matrix I - c J (the paper
+ * simplified Newton corrector on the matrix I - c J, factored as chosen by
+ * ac_integ_opts.linear_solver (see ac_linear_solver) (the paper
  * integrates every cell with the BDF code DLSODES, Sec. 3, and keeps T fixed
  * during the chemistry update, Sec. 5). Rules, identical in the CPU oracle:
  * error test on RMS(d / (atol + rtol |y|)) / (q+1) <= 1; step factor

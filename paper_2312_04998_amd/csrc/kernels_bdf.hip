@@ -1,6 +1,7 @@
 // Batched stiff integrator for gfx950: variable-order (1..5) BDF in
-// backward-difference form with a simplified Newton corrector on the dense
-// Newton matrix I - c J, factored on the FP64 matrix cores.
+// backward-difference form with a simplified Newton corrector on the
+// Newton matrix I - c J: a sparse front swept in levels and the dense Schur
+// tail factored on the FP64 matrix cores (devfront.h), or one dense LU.
 //
 // The paper integrates every cell with DLSODES (Sec. 3) and precomputes the
 // rate coefficients outside the solver; here one persistent workgroup
