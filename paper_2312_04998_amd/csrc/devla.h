@@ -25,7 +25,7 @@ constexpr int SBP = SB + 1;   // its LDS row stride (odd: row-wise lane reads av
 // LDS the factorisation / solves need besides the right-hand side (doubles).
 __host__ __device__ inline int la_scratch_doubles(int n) {
   const int pan = n * PW + PW * PW;
-  const int blk = 2 * SB * SBP;   // the solves' two staged diagonal blocks
+  const int blk = 3 * SB * SBP;   // the solves' two staged diagonal blocks and one off-diagonal
   return pan > blk ? pan : blk;
 }
 
@@ -520,6 +520,69 @@ __device__ __forceinline__ void block_gemv(const double *LU, int lda, int b0, in
   }
 }
 
+// The off-diagonal block of the next step (rows [n0, n0 + ns) x columns
+// [b0, b0 + bs) of M, M as in block_gemv) into LDS (row stride SBP), on NTH
+// threads (t as in stage_block).
+template <int NTH, bool ROWMAJOR>
+__device__ __forceinline__ void stage_off(const double *LU, int lda, int b0, int bs, int n0, int ns,
+                                          double *off, int t) {
+  constexpr int U = (SB * SB + NTH - 1) / NTH;
+  double v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = t + u * NTH;
+    // row-major M: e walks rows of M; column-major: e walks rows of LU
+    const int a = e / SB, q = e - a * SB;
+    bool ok;
+    if (ROWMAJOR) ok = e < SB * SB && a < ns && q < bs;
+    else ok = e < SB * SB && a < bs && q < ns;
+    v[u] = ok ? (ROWMAJOR ? LU[size_t(n0 + a) * lda + b0 + q] : LU[size_t(b0 + a) * lda + n0 + q])
+              : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = t + u * NTH;
+    const int a = e / SB, q = e - a * SB;
+    if (e < SB * SB) {
+      if (ROWMAJOR) off[a * SBP + q] = v[u];
+      else off[q * SBP + a] = v[u];
+    }
+  }
+}
+
+// block_gemv for the rows of the next step, from the staged off-diagonal
+// block (row i - n0 of `off`), with the same per-row sums.
+template <int NTH, bool ROWMAJOR>
+__device__ __forceinline__ void off_gemv(const double *off, int b0, int bs, int n0, int ns, double *x,
+                                         int t) {
+  if constexpr (ROWMAJOR) {
+    const int sub = t & 3;
+    for (int base = 0; base < ns; base += NTH / 4) {
+      const int a = base + (t >> 2);
+      const bool ok = a < ns;
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int q = 4 * u + sub;
+        s += (ok && q < bs ? off[a * SBP + q] : 0.0) * (q < bs ? x[b0 + q] : 0.0);
+      }
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
+      if (ok && sub == 0) x[n0 + a] -= s;
+    }
+  } else {
+    for (int a = t; a < ns; a += NTH) {
+      double s = 0.0;
+      for (int q0 = 0; q0 < bs; q0 += 16) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          s += (q0 + u < bs ? off[a * SBP + q0 + u] : 0.0) * (q0 + u < bs ? x[b0 + q0 + u] : 0.0);
+      }
+      x[n0 + a] -= s;
+    }
+  }
+}
+
 // The chains of the four triangular solves on a staged diagonal block
 // (first wavefront only; x in LDS).
 // L y = b on the block, L unit lower.
@@ -608,12 +671,13 @@ __device__ __forceinline__ void chain_lt(const double *blk, int b0, int bs, doub
 
 // One blocked triangular solve, forward (FWD: blocks from the top) or
 // backward, with a one-block look-ahead: while the first wavefront runs the
-// chain of block k, the other wavefronts stage block k+1 and apply block
-// k-1's columns to the rows beyond block k; then the whole workgroup
-// applies block k's columns to the rows of block k+1, the only rows the
-// next chain needs. Every row receives the blocks' contributions in the
-// same order, each summed the same way, as without the look-ahead.
-// blk: 2 * SB * SBP doubles of LDS.
+// chain of block k, the other wavefronts stage block k+1 and the block of
+// block k's columns on block k+1's rows, and apply block k-1's columns to
+// the rows beyond block k; then the whole workgroup applies block k's
+// columns to the rows of block k+1 (the only rows the next chain needs)
+// from LDS. Every row receives the blocks' contributions in the same
+// order, each summed the same way, as without the look-ahead.
+// blk: 3 * SB * SBP doubles of LDS.
 template <int NT, bool ROWMAJOR, bool FWD, int CHAIN>
 __device__ __forceinline__ void tri_solve(const double *__restrict__ LU, int lda, int n, double *x,
                                           double *blk) {
@@ -635,9 +699,12 @@ __device__ __forceinline__ void tri_solve(const double *__restrict__ LU, int lda
       else chain_lt(cur, b0, bs, x);
     } else {
       const int t = threadIdx.x - 64;
-      if (k + 1 < nb)
+      if (k + 1 < nb) {
         stage_block<NT - 64>(LU, lda, b0_of(k + 1), bs_of(k + 1),
                              blk + ((k + 1) & 1) * (SB * SBP), t);
+        stage_off<NT - 64, ROWMAJOR>(LU, lda, b0, bs, b0_of(k + 1), bs_of(k + 1),
+                                     blk + 2 * (SB * SBP), t);
+      }
       if (k >= 1) {
         // block k-1's columns, rows beyond block k
         const int p0 = b0_of(k - 1), ps = bs_of(k - 1);
@@ -647,9 +714,9 @@ __device__ __forceinline__ void tri_solve(const double *__restrict__ LU, int lda
     }
     __syncthreads();
     if (k + 1 < nb) {
-      // block k's columns, rows of block k+1
+      // block k's columns, rows of block k+1, from the staged block
       const int n0 = b0_of(k + 1), ns_ = bs_of(k + 1);
-      block_gemv<NT, ROWMAJOR>(LU, lda, b0, bs, n0, n0 + ns_, x, threadIdx.x);
+      off_gemv<NT, ROWMAJOR>(blk + 2 * (SB * SBP), b0, bs, n0, ns_, x, threadIdx.x);
       __syncthreads();
     }
   }
@@ -657,7 +724,7 @@ __device__ __forceinline__ void tri_solve(const double *__restrict__ LU, int lda
 
 // Solves with the factors of wg_lu: A x = b (trans = false) or A^T x = b.
 // x (LDS, n doubles) holds b on entry and x on return; tmp (LDS, n
-// doubles) is scratch; blk: 2 * SB * SBP doubles of LDS.
+// doubles) is scratch; blk: 3 * SB * SBP doubles of LDS.
 template <int NT>
 __device__ __forceinline__ void wg_solve(const double *__restrict__ LU, int lda, int n,
                          const int *__restrict__ perm, double *x, double *tmp, bool trans,

@@ -419,7 +419,7 @@ __global__ __launch_bounds__(NT) void k_lu_solve(int n, int lda, int64_t nmat, c
                                                  const int *piv, double *b, int trans) {
   extern __shared__ double sm[];
   double *x = sm, *tmp = sm + n, *blk = tmp + n;
-  int *perm = reinterpret_cast<int *>(blk + 2 * SB * SBP);
+  int *perm = reinterpret_cast<int *>(blk + 3 * SB * SBP);
   for (int64_t m = blockIdx.x; m < nmat; m += gridDim.x) {
     const int *pv = piv + size_t(m) * n;
     if (threadIdx.x == 0) {
@@ -501,7 +501,7 @@ hipError_t launch_lu_solve(int n, int lda, int64_t nmat, const double *LU, const
                            double *b, int trans, hipStream_t st) {
   if (nmat == 0) return hipSuccess;
   const int g = int(nmat < 4096 ? nmat : 4096);
-  const size_t lds = sizeof(double) * (size_t(2) * n + 2 * SB * SBP) + sizeof(int) * size_t(n);
+  const size_t lds = sizeof(double) * (size_t(2) * n + 3 * SB * SBP) + sizeof(int) * size_t(n);
   if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(k_lu_solve<BDF_NT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   hipLaunchKernelGGL(k_lu_solve<BDF_NT>, dim3(g), dim3(BDF_NT), lds, st, n, lda, nmat, LU, piv, b,
