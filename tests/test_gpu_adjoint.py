@@ -35,7 +35,8 @@ def _t(a, dtype=np.float64):
     return torch.from_numpy(np.ascontiguousarray(a, dtype)).cuda()
 
 
-def _adjoint_vs_tangents(acm, oracle_mod, net, y0, T, t_end, lam, n_dir, seed, cap=20000):
+def _adjoint_vs_tangents(acm, oracle_mod, net, y0, T, t_end, lam, n_dir, seed, cap=20000,
+                         solver="auto"):
     """Oracle run (tape) -> GPU adjoint on that tape and oracle tangents on
     that tape; returns (gpu result dict as numpy, oracle replay y, tangents,
     directions)."""
@@ -44,7 +45,7 @@ def _adjoint_vs_tangents(acm, oracle_mod, net, y0, T, t_end, lam, n_dir, seed, c
     N = acm.Network.from_synth(net)
     ws = acm.Workspace(N, n_slots=4)
     out = ws.adjoint(_t(y0), _t(T), acm.tape_from_numpy(ref["tape"]), _t(ref["tape_len"], np.int32),
-                     _t(lam), want_cells=True, want_y=True)
+                     _t(lam), want_cells=True, want_y=True, linear_solver=solver)
     g = {k: v.cpu().numpy() for k, v in out.items()}
     rng = np.random.default_rng(seed)
     n = y0.shape[0]
@@ -94,13 +95,16 @@ def test_adjoint_matches_oracle_tangents_tiny(acm, oracle_mod):
                                atol=1e-13 * np.abs(g["g_cells"]).sum(0).max())
 
 
-def test_adjoint_matches_oracle_tangents_medium(acm, oracle_mod, medium):
-    """Paper-sized network (470 / 4600), one cell, 10 yr of BDF 1-5."""
+@pytest.mark.parametrize("solver", ["auto", "dense"])
+def test_adjoint_matches_oracle_tangents_medium(acm, oracle_mod, medium, solver):
+    """Paper-sized network (470 / 4600), one cell, 10 yr of BDF 1-5, with
+    both Newton solves (the transposed solves of the reverse sweep go
+    through the sparse front and its dense tail, or through one dense LU)."""
     net, cells = medium
     y0, T = cells.y0[:1], cells.T[:1]
     lam = np.random.default_rng(3).standard_normal(y0.shape) / np.maximum(y0, 1e-12)
     g, y_rep, s, dy0, dla = _adjoint_vs_tangents(acm, oracle_mod, net, y0, T, 10 * YEAR_S, lam, 2,
-                                                 2)
+                                                 2, solver=solver)
     assert g["status"].tolist() == [0]
     _check_projection(g, s, lam, dy0, dla)
 
