@@ -55,8 +55,9 @@ def parse():
                    help="cells integrated by both the plain loop and the batched kernel")
     p.add_argument("--plain-max-steps", type=int, default=1000,
                    help="accepted-step budget per cell of that comparison (both sides)")
-    p.add_argument("--adj-cells", type=int, default=32,
-                   help="cells of the adjoint leg (first cells of the 4,096-cell workload)")
+    p.add_argument("--adj-cells", type=int, default=256,
+                   help="cells of the adjoint leg (first cells of the 4,096-cell workload that "
+                        "reach t_end; 256 = one per workgroup slot)")
     p.add_argument("--adj-max-steps", type=int, default=10000)
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain device copy of the densities (known bytes) so HBM "
