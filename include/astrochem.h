@@ -342,8 +342,9 @@ typedef struct {
  * levels of independent pivots, chosen by structure at network build) and
  * factors the Schur complement left over by the remaining, densely coupled
  * species with partial pivoting on the matrix cores. DENSE factors the whole
- * matrix with partial pivoting. The temperature-coupled mode is always
- * DENSE (its temperature row and column are full). */
+ * matrix with partial pivoting. The temperature-coupled mode has its own
+ * plan, over the species and T: its full temperature row and column end in
+ * the dense tail. */
 typedef enum { AC_LINSOLVE_AUTO = 0, AC_LINSOLVE_DENSE = 1 } ac_linear_solver;
 
 /* Per-cell counters written by the integrator ([n_cells][AC_NSTAT]). */

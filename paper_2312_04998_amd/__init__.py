@@ -632,14 +632,16 @@ def _replay(ws, y0, T, tape, tape_len, rtol=1e-6, atol=1e-20, log_alpha=None,
 
 
 def _integrate_thermal(ws, y, T, therm, t_end, rtol=1e-6, atol=1e-20, q_max=5,
-                       max_steps=100000, h0=0.0, log_alpha=None, stream=None):
+                       max_steps=100000, h0=0.0, log_alpha=None, linear_solver="auto",
+                       stream=None):
     import torch
     n = _thermal_args(ws.net, y, T, therm)
     if log_alpha is not None:
         _check_dev(log_alpha, (ws.net.n_reactions,), "log_alpha")
     status = torch.empty(n, dtype=torch.int32, device=y.device)
     stats = torch.empty((n, NSTAT), dtype=torch.int32, device=y.device)
-    o = IntegOpts(float(rtol), float(atol), float(h0), int(q_max), int(max_steps), 0)
+    o = IntegOpts(float(rtol), float(atol), float(h0), int(q_max), int(max_steps), 0, 0, 0.0,
+                  None, _solver(linear_solver))
     check(lib.ac_integrate_thermal(ws.handle, _ptr(log_alpha), n, _ptr(y), _ptr(T), _ptr(therm),
                                    float(t_end), C.byref(o), _ptr(status), _ptr(stats),
                                    _stream(stream)), "ac_integrate_thermal")

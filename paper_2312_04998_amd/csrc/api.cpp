@@ -187,13 +187,33 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
   const size_t o_h0 = p.add(H.jhead0), o_h1 = p.add(H.jhead1), o_td = p.add(H.jtaildesc);
   const size_t o_er = p.add(H.jent_row), o_ec = p.add(H.j_col);
   const size_t o_ht = p.add(H.heat);
-  const ac::FrontPlan &FP = H.front;
-  const size_t o_fperm = p.add(FP.perm), o_flev = p.add(FP.lev_ptr), o_frp = p.add(FP.row_ptr),
-               o_fcol = p.add(FP.col), o_frs = p.add(FP.rsplit), o_fdg = p.add(FP.vdiag),
-               o_fcp = p.add(FP.cptr), o_fcr = p.add(FP.crow), o_fci = p.add(FP.cidx),
-               o_fcs = p.add(FP.csplit), o_fasm = p.add(FP.asm_dst), o_ftp = p.add(FP.tg_ptr),
-               o_ftg = p.add(FP.tgt), o_fop = p.add(FP.op_ptr), o_fops = p.add(FP.ops),
-               o_fgs = p.add(FP.gseg), o_fgp = p.add(FP.gpc);
+  struct FrontOff {
+    size_t perm, lev, rp, col, rs, dg, cp, cr, ci, cs, asmd, tgp, tg, opp, ops, gs, gp, tc, tr;
+  };
+  auto add_front = [&](const ac::FrontPlan &FP) {
+    FrontOff o;
+    o.perm = p.add(FP.perm);
+    o.lev = p.add(FP.lev_ptr);
+    o.rp = p.add(FP.row_ptr);
+    o.col = p.add(FP.col);
+    o.rs = p.add(FP.rsplit);
+    o.dg = p.add(FP.vdiag);
+    o.cp = p.add(FP.cptr);
+    o.cr = p.add(FP.crow);
+    o.ci = p.add(FP.cidx);
+    o.cs = p.add(FP.csplit);
+    o.asmd = p.add(FP.asm_dst);
+    o.tgp = p.add(FP.tg_ptr);
+    o.tg = p.add(FP.tgt);
+    o.opp = p.add(FP.op_ptr);
+    o.ops = p.add(FP.ops);
+    o.gs = p.add(FP.gseg);
+    o.gp = p.add(FP.gpc);
+    o.tc = p.add(FP.tcol_dst);
+    o.tr = p.add(FP.trow_dst);
+    return o;
+  };
+  const FrontOff o_fr = add_front(H.front), o_frth = add_front(H.front_th);
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();
@@ -245,32 +265,40 @@ ac_status ac_net_create(const ac_net_desc *desc, ac_net **out) {
   d.jent_row = at<int32_t>(b, o_er);
   d.jent_col = at<int32_t>(b, o_ec);
   d.heat = H.heat.empty() ? nullptr : at<double>(b, o_ht);
-  ac::DFront &f = d.fr;
-  f.n = FP.n;
-  f.n1 = FP.n1;
-  f.n2 = FP.n2;
-  f.lda2 = FP.lda2;
-  f.vofs = FP.vofs;
-  f.nv = FP.nv;
-  f.n_lev = FP.n_lev;
-  f.perm = at<int32_t>(b, o_fperm);
-  f.lev_ptr = at<int32_t>(b, o_flev);
-  f.row_ptr = at<int32_t>(b, o_frp);
-  f.col = at<int32_t>(b, o_fcol);
-  f.rsplit = at<int32_t>(b, o_frs);
-  f.vdiag = at<int32_t>(b, o_fdg);
-  f.cptr = at<int32_t>(b, o_fcp);
-  f.crow = at<int32_t>(b, o_fcr);
-  f.cidx = at<int32_t>(b, o_fci);
-  f.csplit = at<int32_t>(b, o_fcs);
-  f.asm_dst = at<int32_t>(b, o_fasm);
-  f.tg_ptr = at<int32_t>(b, o_ftp);
-  f.tgt = at<int32_t>(b, o_ftg);
-  f.op_ptr = at<int32_t>(b, o_fop);
-  f.ops = at<int2>(b, o_fops);
-  f.gseg = at<int32_t>(b, o_fgs);
-  f.gpc = at<int2>(b, o_fgp);
-  for (int g = 0; g < 5; ++g) f.gbase[g] = FP.gbase[g];
+  auto dev_front = [&](const ac::FrontPlan &FP, const FrontOff &o) {
+    ac::DFront f{};
+    f.n = FP.n;
+    f.n1 = FP.n1;
+    f.n2 = FP.n2;
+    f.lda2 = FP.lda2;
+    f.vofs = FP.vofs;
+    f.nv = FP.nv;
+    f.n_lev = FP.n_lev;
+    f.perm = at<int32_t>(b, o.perm);
+    f.lev_ptr = at<int32_t>(b, o.lev);
+    f.row_ptr = at<int32_t>(b, o.rp);
+    f.col = at<int32_t>(b, o.col);
+    f.rsplit = at<int32_t>(b, o.rs);
+    f.vdiag = at<int32_t>(b, o.dg);
+    f.cptr = at<int32_t>(b, o.cp);
+    f.crow = at<int32_t>(b, o.cr);
+    f.cidx = at<int32_t>(b, o.ci);
+    f.csplit = at<int32_t>(b, o.cs);
+    f.asm_dst = at<int32_t>(b, o.asmd);
+    f.tg_ptr = at<int32_t>(b, o.tgp);
+    f.tgt = at<int32_t>(b, o.tg);
+    f.op_ptr = at<int32_t>(b, o.opp);
+    f.ops = at<int2>(b, o.ops);
+    f.gseg = at<int32_t>(b, o.gs);
+    f.gpc = at<int2>(b, o.gp);
+    for (int g = 0; g < 5; ++g) f.gbase[g] = FP.gbase[g];
+    f.tcol_dst = FP.tcol_dst.empty() ? nullptr : at<int32_t>(b, o.tc);
+    f.trow_dst = FP.trow_dst.empty() ? nullptr : at<int32_t>(b, o.tr);
+    f.corner_dst = FP.corner_dst;
+    return f;
+  };
+  d.fr = dev_front(H.front, o_fr);
+  d.fr_th = dev_front(H.front_th, o_frth);
   *out = net;
   return AC_OK;
 }

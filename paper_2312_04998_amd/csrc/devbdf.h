@@ -82,6 +82,11 @@ size_t bdf_lds_bytes(const DNet &n);
 inline bool use_front(const DNet &n, const BdfParams &P) {
   return P.linear_solver == AC_LINSOLVE_AUTO && n.fr.n == n.ns && n.fr.n1 > 0;
 }
+// The same for the temperature-coupled state (species + T).
+inline bool use_front_th(const DNet &n, const BdfParams &P) {
+  return P.linear_solver == AC_LINSOLVE_AUTO && n.fr_th.n == n.ns + 1 && n.fr_th.n1 > 0 &&
+         n.fr_th.tcol_dst != nullptr;
+}
 int bdf_resident_blocks(const DNet &n);
 // therm non-null selects the temperature-coupled mode (state ns + 1 per
 // cell, therm [n_cells][3] = (c_v, T_b, lambda)).

@@ -81,11 +81,14 @@ __device__ __forceinline__ double gather_sum(const DFront &F, int g, int r, cons
 // front pivots level by level, then S factored with partial pivoting
 // (wg_lu: piv, perm2 of n2 entries). Returns 0, or 1 + the position of a
 // zero pivot (the front's first, else the tail's).
+// Jaux (temperature-coupled plan only, else null): the Jacobian's T column,
+// T row and corner after the pattern values.
 template <int NT>
-__device__ __forceinline__ int front_factor(const DNet &n, const double *__restrict__ Jg, double c,
+__device__ __forceinline__ int front_factor(const DNet &n, const DFront &F,
+                                            const double *__restrict__ Jg,
+                                            const double *__restrict__ Jaux, double c,
                                             double *M, int *piv, int *perm2, double *pan,
                                             double *red, int *redi, int *ipiv) {
-  const DFront &F = n.fr;
   double *S = M, *V = M + F.vofs;
   const int n2 = F.n2, lda2 = F.lda2;
   if (threadIdx.x == 0) redi[0] = INT_MAX;
@@ -115,6 +118,23 @@ __device__ __forceinline__ int front_factor(const DNet &n, const double *__restr
         if (dst[u] >= 0) V[dst[u]] = v;
         else S[-1 - dst[u]] = v;
       }
+  }
+  if (Jaux) {
+    const int ns = n.ns;
+    for (int i = threadIdx.x; i < ns; i += NT) {
+      const int d1 = F.tcol_dst[i], d2 = F.trow_dst[i];
+      const double v1 = -c * Jaux[i], v2 = -c * Jaux[ns + i];
+      if (d1 >= 0) V[d1] = v1;
+      else S[-1 - d1] = v1;
+      if (d2 >= 0) V[d2] = v2;
+      else S[-1 - d2] = v2;
+    }
+    if (threadIdx.x == 0) {
+      const int d3 = F.corner_dst;
+      const double v3 = 1.0 - c * Jaux[2 * ns];
+      if (d3 >= 0) V[d3] = v3;
+      else S[-1 - d3] = v3;
+    }
   }
   __syncthreads();
   for (int l = 0; l < F.n_lev; ++l) {

@@ -36,6 +36,9 @@ struct DFront {
   const int32_t *gseg;   // [4 (n + 1)] pieces of each output of the solves' four gathers
   const int2 *gpc;       // entry range of every piece
   int gbase[5];          // first piece of each gather
+  // temperature-coupled plan only: destinations of the T column, T row, corner
+  const int32_t *tcol_dst, *trow_dst;
+  int corner_dst;
 };
 
 struct DNet {
@@ -49,7 +52,8 @@ struct DNet {
   const uint32_t *jhead0, *jhead1, *jtaildesc;
   const int32_t *jent_row, *jent_col;   // row and column of every pattern entry
   const double *heat;          // [nr] energy per reaction event (temperature-coupled mode) or null
-  DFront fr;
+  DFront fr;                   // Newton-solve plan of the species state
+  DFront fr_th;                // and of the temperature-coupled state (species + T)
 };
 
 // Launchers (kernels_chem.hip). All enqueue on `stream`; return hipError_t.

@@ -149,8 +149,8 @@ template <int NT>
 __device__ __forceinline__ void cell_factor(CellCtx &cx, double c) {
   const DNet &n = *cx.n;
   if (cx.front) {
-    cx.lu_info = front_factor<NT>(n, cx.Jg, c, cx.M, cx.piv, cx.perm, cx.scr, cx.red, cx.redi,
-                                  cx.ipiv);
+    cx.lu_info = front_factor<NT>(n, n.fr, cx.Jg, nullptr, c, cx.M, cx.piv, cx.perm, cx.scr,
+                                  cx.red, cx.redi, cx.ipiv);
     cx.cnt[ST_LU]++;
     return;
   }
@@ -246,10 +246,17 @@ __device__ __forceinline__ void cell_jac_th(CellCtx &cx, const double *y) {
   cell_jac<NT>(cx, y);   // pattern values with the refreshed coefficients
 }
 
-// M = I - c J over the coupled state (ns + 1), then LU.
+// M = I - c J over the coupled state (ns + 1), then its factors: the
+// sparse front of the coupled state's plan when cx.front, else one LU.
 template <int NT>
 __device__ __forceinline__ void cell_factor_th(CellCtx &cx, double c) {
   const DNet &n = *cx.n;
+  if (cx.front) {
+    cx.lu_info = front_factor<NT>(n, n.fr_th, cx.Jg, cx.Jaux, c, cx.M, cx.piv, cx.perm, cx.scr,
+                                  cx.red, cx.redi, cx.ipiv);
+    cx.cnt[ST_LU]++;
+    return;
+  }
   const int ns = n.ns, nv = ns + 1, lda = cx.lda;
   for (int e = threadIdx.x; e < nv * lda; e += NT) {
     const int i = e / lda, a = e - i * lda;
@@ -292,8 +299,8 @@ __device__ __forceinline__ void cell_factor_any(CellCtx &cx, double c) {
 // cx.tmp and cx.scr as scratch.
 template <int NT, bool TH>
 __device__ __forceinline__ void cell_solve(CellCtx &cx, double *x, bool trans) {
-  if (!TH && cx.front)
-    front_solve<NT>(cx.n->fr, cx.M, cx.perm, x, cx.tmp, trans, cx.scr);
+  if (cx.front)
+    front_solve<NT>(TH ? cx.n->fr_th : cx.n->fr, cx.M, cx.perm, x, cx.tmp, trans, cx.scr);
   else
     wg_solve<NT>(cx.M, cx.lda, cx.n->ns + (TH ? 1 : 0), cx.perm, x, cx.tmp, trans, cx.scr);
 }

@@ -331,4 +331,34 @@ FrontPlan build_front_plan(int n, const std::vector<int32_t> &j_row_ptr,
   return F;
 }
 
+FrontPlan build_front_plan_thermal(int ns, const std::vector<int32_t> &j_row_ptr,
+                                   const std::vector<int32_t> &j_col, size_t max_doubles) {
+  // augmented CSR: every species row gains the column T (= ns, last), then
+  // the row T is full
+  const int nnz = j_row_ptr[ns];
+  std::vector<int32_t> rp(ns + 2), col;
+  col.reserve(size_t(nnz) + 2 * size_t(ns) + 1);
+  for (int r = 0; r < ns; ++r) {
+    rp[r] = int32_t(col.size());
+    for (int e = j_row_ptr[r]; e < j_row_ptr[r + 1]; ++e) col.push_back(j_col[e]);
+    col.push_back(ns);
+  }
+  rp[ns] = int32_t(col.size());
+  for (int a = 0; a <= ns; ++a) col.push_back(a);
+  rp[ns + 1] = int32_t(col.size());
+  FrontPlan F = build_front_plan(ns + 1, rp, col, max_doubles);
+  if (F.n1 == 0) return F;
+  const std::vector<int32_t> aug = F.asm_dst;
+  F.asm_dst.resize(nnz);
+  F.tcol_dst.resize(ns);
+  F.trow_dst.resize(ns);
+  for (int r = 0; r < ns; ++r) {
+    for (int e = j_row_ptr[r]; e < j_row_ptr[r + 1]; ++e) F.asm_dst[e] = aug[size_t(e) + r];
+    F.tcol_dst[r] = aug[size_t(j_row_ptr[r + 1]) + r];
+  }
+  for (int a = 0; a < ns; ++a) F.trow_dst[a] = aug[size_t(nnz) + ns + a];
+  F.corner_dst = aug[size_t(nnz) + 2 * size_t(ns)];
+  return F;
+}
+
 }  // namespace ac

@@ -69,6 +69,11 @@ struct FrontPlan {
   std::vector<int32_t> gpc;       // [2 n_piece]
   int gbase[5] = {0, 0, 0, 0, 0};
   double cost_front = 0.0, cost_dense = 0.0;   // modelled seconds per factorisation
+  // Temperature-coupled state only (n = species + 1): destinations of the
+  // temperature column (one per species), the temperature row and the
+  // corner, coded as asm_dst (whose entries are the species pattern's).
+  std::vector<int32_t> tcol_dst, trow_dst;
+  int32_t corner_dst = 0;
 };
 
 constexpr int FRONT_PIECE = 16;
@@ -78,5 +83,10 @@ constexpr int FRONT_MAX_PIECES = 8192;   // partial sums per gather (doubles of 
 // Newton matrix region holds max_doubles doubles per slot.
 FrontPlan build_front_plan(int n, const std::vector<int32_t> &j_row_ptr,
                            const std::vector<int32_t> &j_col, size_t max_doubles);
+
+// The plan for the temperature-coupled state (ns species + T): the
+// species pattern with a full temperature row and column.
+FrontPlan build_front_plan_thermal(int ns, const std::vector<int32_t> &j_row_ptr,
+                                   const std::vector<int32_t> &j_col, size_t max_doubles);
 
 }  // namespace ac

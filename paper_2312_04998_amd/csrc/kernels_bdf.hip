@@ -85,7 +85,7 @@ __global__ __launch_bounds__(NT) void k_bdf(DNet n, const double *__restrict__ l
   cx.nc = n.n_cond;
   cx.la_over = la_over;
   cx.Jaux = cx.Jg + n.nnz_j;
-  cx.front = FR && !TH;
+  cx.front = FR;
   const double rtol = P.rtol, atol = P.atol, t_end = P.t_end;
   const double tol = P.newton_tol > 0.0
                          ? P.newton_tol
@@ -469,7 +469,7 @@ hipError_t launch_bdf(const DNet &n, const double *la, int64_t n_cells, double *
                       hipStream_t st) {
   if (n_cells == 0) return hipSuccess;
   const size_t lds = bdf_lds_bytes(n);
-  auto kern = therm ? k_bdf<BDF_NT, true, false>
+  auto kern = therm ? (use_front_th(n, P) ? k_bdf<BDF_NT, true, true> : k_bdf<BDF_NT, true, false>)
                     : use_front(n, P) ? k_bdf<BDF_NT, false, true> : k_bdf<BDF_NT, false, false>;
   if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));

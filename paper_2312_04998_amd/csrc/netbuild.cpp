@@ -427,6 +427,7 @@ std::string build_network(int ns, int nr, const int32_t *reactants, const int32_
     std::memcpy(p2, half, sizeof(half));
   }
   H.front = build_front_plan(ns, H.j_row_ptr, H.j_col, newton_region_doubles(ns));
+  H.front_th = build_front_plan_thermal(ns, H.j_row_ptr, H.j_col, newton_region_doubles(ns));
   *code = AC_OK;
   return "";
 }

@@ -95,6 +95,7 @@ struct HostNet {
   Schedule jtail;
   Schedule gy;                        // species a: items (j, other reactant, mult) over slots of a
   FrontPlan front;                    // the integrator's Newton solve (sparse front, dense tail)
+  FrontPlan front_th;                 // the same for the temperature-coupled state
   int layout = 0, ordering = 0;
 };
 

@@ -140,3 +140,32 @@ def test_thermal_closed_form_and_energy(acm, oracle_mod, medium_net):
     scale = th[:, 0] * y0[:, -1] + np.abs(y0[:, :-1]) @ np.abs(h)
     assert np.all(np.abs(E1 - E0) <= 1e-9 * scale)
     assert np.all(np.abs(y1[:, -1] - y0[:, -1]) > 1e-3)
+
+
+def test_thermal_front_equals_dense_solve(acm, medium_net):
+    """Paper-sized network with reaction heats: the temperature-coupled
+    integration with the sparse-front Newton solve of the coupled state (T
+    in the dense tail) and with one dense LU agree, both reaching t_end, to
+    the integration tolerance (rtol 1e-6) above the 1e-20 floor; both keep
+    the conserved energy."""
+    net, h, cells, y0, th = _thermal(medium_net, 3, 4)
+    N = acm.Network.from_synth(net)
+    ws = acm.Workspace(N, n_slots=3)
+    outs = {}
+    for solver in ("auto", "dense"):
+        yd = _t(y0)
+        out = ws.integrate_thermal(yd, _t(cells.T), _t(th), 1e3 * YEAR_S, linear_solver=solver)
+        assert out["status"].cpu().tolist() == [0, 0, 0], solver
+        outs[solver] = (yd.cpu().numpy(), out["stats"].cpu().numpy())
+    ya, sa = outs["auto"]
+    yd_, sd = outs["dense"]
+    big = np.maximum(np.abs(ya), np.abs(yd_)) > 1e-20
+    rel = np.abs(ya - yd_)[big] / np.maximum(np.abs(ya), np.abs(yd_))[big]
+    print(f"auto vs dense: max rel diff {rel.max():.2e}; steps {sa[:, 0].tolist()} vs {sd[:, 0].tolist()}")
+    assert rel.max() <= 1e-5
+    for y1 in (ya, yd_):
+        E0 = th[:, 0] * y0[:, -1] + y0[:, :-1] @ h
+        E1 = th[:, 0] * y1[:, -1] + y1[:, :-1] @ h
+        scale = th[:, 0] * y0[:, -1] + np.abs(y0[:, :-1]) @ np.abs(h)
+        assert np.all(np.abs(E1 - E0) <= 1e-9 * scale)
+
