@@ -64,6 +64,8 @@ struct SchedOff {
 };
 
 static_assert(ac::RUN_LEN == ac::RUN_ITEMS, "host and device run lengths differ");
+static_assert(ac::FRONT_MAX_PIECES <= 3 * ac::SB * ac::SBP,
+              "the front gathers' partial sums must fit the solves' LDS block");
 
 SchedOff add_sched(Packer &p, const ac::Schedule &s) {
   SchedOff o;
